@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def c1():
+    from paper_1811_03510_amd import scenes
+    return scenes.config1()
+
+
+@pytest.fixture(scope="session")
+def c1_oracle(c1):
+    import oracle
+    return oracle.Scene(c1.cp, c1.types, c1.leaf_depth)
