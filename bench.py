@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of closest-hit ray intersection with Catmull-Clark patch scenes.
+
+Workload (default): 1,000,000 patches (2000 seeded displaced tori / apple tori,
+25 % Gregory, leaf depth 10), 1920x1080 pinhole primary rays plus one secondary
+ray per pixel (cosine-weighted bounce from seeded surface points).  Synthetic,
+seeded, generated on the host and resident in HBM before timing starts.
+
+A step is one intersection launch over all primary rays followed by one over
+all secondary rays (the whole hot path per batch).  W warm-up steps, then K
+steps timed with HIP events recorded on the stream the kernels run on.  Prints
+one JSON line.  The CPU baseline times the FP64 oracle on a bounded seeded
+sample of the same rays on the host cores and reports the parity of that sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MRays/s primary+diffuse at 1M patches: plain vs learned-order batched, oracle-exact"
+
+# Algorithmic 32-bit VALU operations per counted unit of work (fp32 add, mul,
+# fma, 2- or 3-operand min/max, compare, select, bit op: 1 each; a de Casteljau
+# midpoint (a+b)/2: 2; a division: 1).  Derived from the method's arithmetic,
+# not from the compiled code; the derivation is in the design doc.
+OPS_PER_UNIT = {
+    "ray": 25,         # ray setup (validity, reciprocals) and the hit write
+    "node": 44,        # BVH node: two slab tests, ordering, stack push
+    "cand": 12,        # candidate patch: anchored origin and its products
+    "split": 334,      # Alg. 3 step: split 4x4x3 at 1/2, two boxes, two slab tests, choice, path bits
+    "backtrack": 6,    # count-trailing-zeros, path and trail update
+    "greg": 622,       # Alg. 2 on a domain: extreme blends, displacement, crop of the lower grid
+    "leaf": 30,        # leaf record: compare, (u, v) from the path code
+    "crop": 502,       # Bezier grid recompute after backtracking (crop to the domain)
+}
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x clock: 39.32 T lane-op/s
+COUNTERS = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1811_03510_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_ops(cnt: np.ndarray) -> float:
+    tot = cnt.astype(np.float64).sum(axis=0)
+    ops = OPS_PER_UNIT["ray"] * cnt.shape[0]
+    for k, name in enumerate(COUNTERS):
+        ops += OPS_PER_UNIT.get(name, 0) * tot[k]
+    return float(ops)
+
+
+def traffic_from_profiles(kernel_ms_avg: float):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE), scaled
+    by the copy-kernel calibration, when recorded for the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "intersect_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["instanced1m", "torus512"], default="instanced1m")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-counters", action="store_true", help="skip the counted launch (roofline)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU: every ray is independent, so N GPUs "
+                                   "would each run this same benchmark on 1/N of the rays; use --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1811_03510_amd import ccs, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    w = scenes.config2() if args.workload == "instanced1m" else scenes.config1()
+    gen_s = time.time() - t0
+    log(f"workload {w.name}: {w.cp.shape[0]} patches, {len(w.primary)} + {len(w.diffuse)} rays "
+        f"(generated in {gen_s:.1f} s)")
+    t0 = time.time()
+    scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
+    torch.cuda.synchronize()
+    create_s = time.time() - t0
+    info = scene.info()
+    log(f"scene: {info['n_nodes']} nodes, BVH depth {info['bvh_depth']}, {info['device_bytes'] / 2**20:.1f} MiB, "
+        f"create {create_s:.2f} s (host BVH {info['build_seconds']:.2f} s)")
+
+    prim = torch.from_numpy(w.primary).cuda()
+    diff = torch.from_numpy(w.diffuse).cuda()
+    hp = torch.empty((prim.shape[0], 4), dtype=torch.float32, device="cuda")
+    hd = torch.empty((diff.shape[0], 4), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        if evs:
+            evs[0].record(stream)
+        scene.intersect(prim, hp)
+        if evs:
+            evs[1].record(stream)
+        scene.intersect(diff, hd)
+        if evs:
+            evs[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    tp = np.array([e[0].elapsed_time(e[1]) for e in events])
+    td = np.array([e[1].elapsed_time(e[2]) for e in events])
+    total_ms = events[0][0].elapsed_time(events[-1][2])
+    ms_step = total_ms / args.steps
+    n_p, n_d = prim.shape[0], diff.shape[0]
+    value = (n_p + n_d) / (ms_step * 1e-3) / 1e6
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, primary {np.median(tp):.3f} ms, "
+        f"secondary {np.median(td):.3f} ms -> {value:.1f} MRays/s")
+
+    hits_p, hits_d = hp.cpu().numpy(), hd.cpu().numpy()
+    per_class = {
+        "primary": {"rays": n_p, "ms_median": float(np.median(tp)), "ms_p10": float(np.percentile(tp, 10)),
+                    "ms_p90": float(np.percentile(tp, 90)), "mrays_per_s": n_p / np.median(tp) / 1e3,
+                    "hit_fraction": float((ccs.hit_ids(hits_p) != ccs.NO_HIT).mean())},
+        "diffuse": {"rays": n_d, "ms_median": float(np.median(td)), "ms_p10": float(np.percentile(td, 10)),
+                    "ms_p90": float(np.percentile(td, 90)), "mrays_per_s": n_d / np.median(td) / 1e3,
+                    "hit_fraction": float((ccs.hit_ids(hits_d) != ccs.NO_HIT).mean())},
+    }
+
+    roofline = None
+    work = None
+    if not args.no_counters:
+        _, cp_ = scene.intersect_counted(prim)
+        _, cd_ = scene.intersect_counted(diff)
+        torch.cuda.synchronize()
+        cp_, cd_ = cp_.cpu().numpy(), cd_.cpu().numpy()
+        ops_p, ops_d = algorithmic_ops(cp_), algorithmic_ops(cd_)
+        launch_ms = float(np.mean(tp) + np.mean(td)) / 2.0
+        achieved = (ops_p + ops_d) / ((np.mean(tp) + np.mean(td)) * 1e-3) / 1e12
+        bytes_launch = traffic_from_profiles(launch_ms)
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
+                    "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                    "traffic": bytes_launch, "kernel": "k_intersect<false>",
+                    "kernel_avg_ms": round(launch_ms, 4),
+                    "ops_per_launch": (ops_p + ops_d) / 2.0,
+                    "ops_per_ray": {"primary": ops_p / n_p, "diffuse": ops_d / n_d}}
+        work = {c: {"primary": float(cp_[:, k].mean()), "diffuse": float(cd_[:, k].mean())}
+                for k, c in enumerate(COUNTERS)}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.parity import gate
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+        threads = min(threads, os.cpu_count() or threads)
+        t0 = time.time()
+        osc = oracle.Scene(w.cp, w.types, w.leaf_depth)
+        obuild = time.time() - t0
+        calib = scenes.sample_indices(n_p, 1024, seed=91)
+        t0 = time.time()
+        osc.intersect(w.primary[calib], nthreads=threads)
+        osc.intersect(w.diffuse[calib], nthreads=threads)
+        per_ray = (time.time() - t0) / (2 * len(calib))
+        k = int(min(max(2048, args.cpu_seconds / max(per_ray, 1e-9) / 2), n_p, n_d))
+        sel_p = scenes.sample_indices(n_p, k, seed=92)
+        sel_d = scenes.sample_indices(n_d, k, seed=93)
+        t0 = time.time()
+        op = osc.intersect(w.primary[sel_p], nthreads=threads)
+        od = osc.intersect(w.diffuse[sel_d], nthreads=threads)
+        osec = time.time() - t0
+        cpu = {"value": round(2 * k / osec / 1e6, 4), "unit": "MRays/s", "cores": threads, "kind": "oracle",
+               "sample": f"{k} primary + {k} secondary rays (seeded subset of the same {n_p}+{n_d} rays), "
+                         f"{osec:.1f} s; oracle BVH build {obuild:.1f} s excluded"}
+        rp = gate(hits_p[sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="primary")
+        rd = gate(hits_d[sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="diffuse")
+        parity = {c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
+                      "excused": r["excused"], "ok": r["ok"]} for c, r in (("primary", rp), ("diffuse", rd))}
+        log(f"cpu baseline: {cpu['value']} MRays/s on {threads} threads; parity {parity}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "MRays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": (f"{w.name}: {w.cp.shape[0]} patches "
+                                f"({int(w.types.sum())} Gregory), {n_p} primary + {n_d} secondary rays per step"),
+                   "variant": "plain (closest-first order, one launch per ray class)",
+                   "leaf_depth": w.leaf_depth},
+        "per_class": per_class,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "work_per_ray": work,
+        "scene": {"create_s": round(create_s, 3), "bvh_build_s": round(info["build_seconds"], 3),
+                  "bvh_depth": info["bvh_depth"], "device_mib": round(info["device_bytes"] / 2**20, 1)},
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

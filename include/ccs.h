@@ -1,0 +1,163 @@
+/*
+ * ccs.h -- closest-hit ray intersection with Catmull-Clark subdivision surfaces
+ * in patch form (bicubic Bezier and Gregory patches) on AMD Instinct MI355X.
+ *
+ * The method is the stackless hierarchical subdivision of Binder & Keller,
+ * "Massively Parallel Stackless Ray Tracing of Catmull-Clark Subdivision
+ * Surfaces" (arXiv:1811.03510): a BVH over patch bounds (Sec. 4, results
+ * discussion), then per candidate patch the bit-trail subdivision of Alg. 3 with
+ * Bezier bounds on subdomains (Sec. 3.1, Alg. 1) and Gregory bounds from Alg. 2
+ * (Sec. 3.2).  The reported hit is the entry distance into the closest leaf box
+ * together with the centre of the leaf's parameter domain: Sec. 3 states that
+ * intersecting the nested boxes alone yields the intersection up to almost
+ * floating-point precision.
+ *
+ * Conventions shared by every entry point
+ *   - Patch input: n x 20 x 3 floats (fp32), patch-major.  Slot s of a patch
+ *     holds point s as (x, y, z).  Slots 0..15 are the 4x4 grid,
+ *     slot(i, j) = 4*j + i with i along u and j along v (Sec. 3.1).  For a
+ *     Gregory patch (Sec. 3.2) slots 5, 6, 9, 10 hold P^u of the inner points
+ *     (1,1), (2,1), (1,2), (2,2) and slots 16..19 hold P^v in the same order; the
+ *     inner point is (du P^u + dv P^v) / (du + dv) with du = u or 1-u and
+ *     dv = v or 1-v for i = 1 or 2 and j = 1 or 2 (the weighting of Alg. 2).
+ *     A Bezier patch ignores slots 16..19.
+ *   - Patch types: n bytes, CCS_BEZIER (0) or CCS_GREGORY (1).
+ *   - Leaf depth L: each patch is subdivided L times along u and L times along v
+ *     (alternating, u first, Sec. 3.3); domains are integers in units of 2^-23
+ *     (Alg. 3).  1 <= L <= 16.
+ *   - Rays: ccs_ray, 32 bytes.  A hit t is in units of the given (not
+ *     necessarily unit) direction and lies in [tmin, tmax] (closed).  Rays with a
+ *     non-finite origin or direction, a zero direction or tmin > tmax miss.
+ *   - Hits: ccs_hit, 16 bytes.  A miss is {t = +inf, patch_id = CCS_NO_HIT,
+ *     u = 0, v = 0}.  Among equal distances the smaller patch id wins.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Functions marked asynchronous only enqueue work on that stream.
+ *   - Errors: every entry point returns a ccs_status; no exception crosses the
+ *     boundary.  ccs_last_error() gives a message for the calling thread.
+ */
+#ifndef CCS_H
+#define CCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCS_NO_HIT 0xFFFFFFFFu
+#define CCS_MAX_LEAF_DEPTH 16
+
+typedef enum ccs_status {
+  CCS_OK = 0,
+  CCS_ERR_INVALID_ARG = 1, /* null pointer, bad tag, L out of range, non-finite input, size mismatch */
+  CCS_ERR_OOM = 2,         /* device or host allocation failed */
+  CCS_ERR_HIP = 3,         /* a HIP runtime call failed; see ccs_last_error() */
+  CCS_ERR_UNSUPPORTED = 4  /* no gfx950 device, or a flag this build does not support */
+} ccs_status;
+
+typedef enum ccs_patch_type { CCS_BEZIER = 0, CCS_GREGORY = 1 } ccs_patch_type;
+
+typedef enum ccs_location { CCS_HOST = 0, CCS_DEVICE = 1 } ccs_location;
+
+/* Ray {o, tmin, d, tmax}: float4-aligned so that one ray is two 16-byte loads. */
+typedef struct ccs_ray {
+  float ox, oy, oz, tmin;
+  float dx, dy, dz, tmax;
+} ccs_ray;
+
+/* Closest hit: entry distance into the leaf box, patch index into the input
+ * arrays, and the centre (u, v) of the leaf domain (Alg. 3's intersection
+ * record (pos, size) expressed as a point). */
+typedef struct ccs_hit {
+  float t;
+  uint32_t patch_id;
+  float u, v;
+} ccs_hit;
+
+typedef struct ccs_scene ccs_scene;
+
+typedef struct ccs_scene_desc {
+  const float* control_points;  /* n x 20 x 3 fp32, layout above; host or device (see location) */
+  const uint8_t* patch_types;   /* n tags; same location as control_points */
+  uint32_t n_patches;           /* 0 <= n < 2^31; an empty scene makes every ray miss */
+  int32_t location;             /* CCS_HOST or CCS_DEVICE */
+  uint32_t leaf_depth;          /* L, 1..16 */
+  uint32_t flags;               /* must be 0 */
+  void* stream;                 /* hipStream_t used for the uploads */
+} ccs_scene_desc;
+
+typedef struct ccs_scene_info {
+  uint32_t n_patches;
+  uint32_t n_nodes;       /* BVH nodes (binary, one patch per leaf) */
+  uint32_t leaf_depth;
+  uint32_t bvh_depth;     /* deepest leaf */
+  uint64_t device_bytes;  /* device memory owned by the scene */
+  float lo[3], hi[3];     /* scene bounds (union of patch boxes) */
+  double build_seconds;   /* host BVH build time */
+} ccs_scene_info;
+
+/* Builds a scene (Sec. 3: patch bounds, then a hierarchy over them).
+ * Validates on the host: non-null pointers, tags in {0, 1}, 1 <= L <= 16,
+ * finite control points (device inputs are copied to the host to be scanned).
+ * Computes per patch an anchor (the fp32 centre of its box; Sec. 3.4 anchors
+ * patches at the origin for precision), the anchored control points and the
+ * hull box of its 16 or 20 points (Sec. 3.1, 3.2), builds a binary BVH with
+ * binned SAH splits on the host (Sec. 4), and uploads everything.
+ * Synchronous: on return the caller may free its buffers; the scene owns every
+ * device buffer it uses.  Errors: CCS_ERR_INVALID_ARG, CCS_ERR_OOM, CCS_ERR_HIP,
+ * CCS_ERR_UNSUPPORTED (no gfx950 device).  *out is NULL on error. */
+ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out);
+
+/* Moves the control points of an existing scene (animation playback, the use
+ * case named in the abstract).  Same n, same tags, same layout as at creation.
+ * Anchors stay at their creation values.  On the GPU: anchored points and patch
+ * boxes are recomputed and the BVH node boxes are refitted bottom-up; the
+ * topology is unchanged.  Asynchronous on `stream`; device input must stay
+ * valid until the stream passes this call.  Host input is copied before return.
+ * Host input is scanned for non-finite values (CCS_ERR_INVALID_ARG); device input
+ * is not scanned (non-finite points then give unspecified hits, never a fault). */
+ccs_status ccs_refit(ccs_scene* scene, const float* control_points, int32_t location, void* stream);
+
+/* Closest hits of n rays (Alg. 3 per candidate patch, candidates from the BVH
+ * nearest first, the best distance so far pruning both).  rays and hits are
+ * device pointers owned by the caller; n == 0 is a no-op.  Asynchronous on
+ * `stream`.  Deterministic: the result of each ray does not depend on launch
+ * geometry or on the other rays. */
+ccs_status ccs_intersect(const ccs_scene* scene, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
+                         void* stream);
+
+/* As ccs_intersect, and also writes per-ray work counters (device, n x 8
+ * uint32): BVH nodes visited, candidate patches, subdivision steps (Alg. 3
+ * splits), backtracks, Gregory bound recomputations (Alg. 2, including each
+ * Gregory candidate's root), leaf records, Bezier grid re-crops after
+ * backtracking (Alg. 1), Gregory candidates.  A separately compiled copy of the
+ * same kernel; used for measurement. */
+ccs_status ccs_intersect_counted(const ccs_scene* scene, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
+                                 uint32_t* counters, void* stream);
+
+/* Secondary rays from hits (Sec. 3.3, self-intersection): for hit i the origin is
+ * o + t d moved along the unit normal f_u x f_v at (u, v) (turned against d) by
+ * the L1 size of the box of the leaf domain containing (u, v) (Alg. 2 bounds on
+ * that domain); the direction is cosine-weighted about the normal from the two
+ * uniforms uniforms[2i], uniforms[2i+1] in [0, 1) (Malley's method; polar disk
+ * map; tangent frame of Duff et al. 2017).  A miss gives an inactive ray
+ * {o = 0, tmin = 0, d = (0, 0, 1), tmax = -1}.  All pointers are device pointers
+ * of n elements; out_rays may not alias rays.  Asynchronous on `stream`. */
+ccs_status ccs_bounce(const ccs_scene* scene, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
+                      uint32_t n, ccs_ray* out_rays, void* stream);
+
+ccs_status ccs_scene_info_get(const ccs_scene* scene, ccs_scene_info* info);
+
+/* Frees every device buffer of the scene (synchronizes the device first).  NULL is a no-op. */
+void ccs_scene_destroy(ccs_scene* scene);
+
+/* Message of the last failing call on this thread ("" if none).  Valid until the
+ * next ccs_* call on the same thread. */
+const char* ccs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCS_H */

@@ -18,7 +18,7 @@ from . import build as _build
 
 _lib = None
 NO_HIT = 0xFFFFFFFF
-COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf")
+COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
 
 
 def lib():
@@ -142,12 +142,12 @@ class Scene:
         return int(lib().orc_scene_nodes(self._h))
 
     def intersect(self, rays, nthreads: int = 0, counters: bool = False):
-        """Closest hits: dict(t, id, u, v[, counters (n, 6)])."""
+        """Closest hits: dict(t, id, u, v[, counters (n, 8), see COUNTER_NAMES])."""
         r = np.ascontiguousarray(rays, dtype=np.float32).reshape(-1, 8)
         n = r.shape[0]
         t, u, v = np.zeros(n), np.zeros(n), np.zeros(n)
         ids = np.zeros(n, dtype=np.uint32)
-        cnt = np.zeros((n, 6), dtype=np.uint32) if counters else None
+        cnt = np.zeros((n, 8), dtype=np.uint32) if counters else None
         lib().orc_intersect(self._h, _p(r, C.c_float), n, nthreads, _p(t, C.c_double),
                             _p(ids, C.c_uint32), _p(u, C.c_double), _p(v, C.c_double),
                             _p(cnt, C.c_uint32) if counters else None)

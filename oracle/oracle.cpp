@@ -74,7 +74,7 @@ struct Best {
 };
 
 struct Counters {  // per ray
-  uint32_t node, cand, split, backtrack, greg, leaf;
+  uint32_t node, cand, split, backtrack, greg, leaf, crop, cand_greg;
 };
 
 // ------------------------------------------------------------------ evaluation
@@ -379,6 +379,7 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
     stack.pop_back();
     if (f.second) {
       c.backtrack++;
+      if (!P.gregory) c.crop++;  // Alg. 3 re-crops a Bezier grid after backtracking
       if (P.gregory) {
         Bound b = calc_points_and_d_int(P, f.pu, f.pv, f.su, f.sv);
         c.greg++;
@@ -509,6 +510,7 @@ static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
       double e;
       if (!slab(r, S.patches[k].lo, S.patches[k].hi, best.t, &e)) continue;
       c.cand++;
+      c.cand_greg += S.patches[k].gregory;
       intersect_patch(S.patches[k], k, r, S.L, best, c, nullptr);
     }
     return;
@@ -526,6 +528,7 @@ static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
         uint32_t id = S.order[k];
         if (!slab(r, S.patches[id].lo, S.patches[id].hi, best.t, &e)) continue;
         c.cand++;
+        c.cand_greg += S.patches[id].gregory;
         intersect_patch(S.patches[id], id, r, S.L, best, c, nullptr);
       }
       continue;
@@ -801,23 +804,25 @@ uint32_t orc_scene_nodes(void* s) { return (uint32_t)((Scene*)s)->nodes.size(); 
 
 // Closest hits of n rays (n x 8 floats: o, tmin, d, tmax).  Outputs per ray: t
 // (tmax if no hit), patch id (0xFFFFFFFF if none), u, v and, if counters is
-// non-null, six counters: BVH nodes, candidate patches, split steps,
-// backtracks, Gregory recomputes, leaf records.
+// non-null, eight counters: BVH nodes, candidate patches, split steps,
+// backtracks, Gregory bound recomputations, leaf records, Bezier re-crops after
+// backtracking, Gregory candidates.
 void orc_intersect(void* s, const float* rays, uint32_t n, int nthreads, double* t, uint32_t* id,
                    double* u, double* v, uint32_t* counters) {
   const Scene& S = *(Scene*)s;
   parallel_for(n, nthreads, [&](uint32_t i) {
     Ray r = load_ray(rays + 8 * (size_t)i);
     Best b;
-    Counters c = {0, 0, 0, 0, 0, 0};
+    Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
     trace_ray(S, r, b, c);
     t[i] = b.t;
     id[i] = b.id;
     u[i] = b.u;
     v[i] = b.v;
     if (counters) {
-      uint32_t* o = counters + 6 * (size_t)i;
-      o[0] = c.node; o[1] = c.cand; o[2] = c.split; o[3] = c.backtrack; o[4] = c.greg; o[5] = c.leaf;
+      uint32_t* o = counters + 8 * (size_t)i;
+      o[0] = c.node; o[1] = c.cand; o[2] = c.split; o[3] = c.backtrack;
+      o[4] = c.greg; o[5] = c.leaf; o[6] = c.crop; o[7] = c.cand_greg;
     }
   });
 }
@@ -830,7 +835,7 @@ int orc_trace_patch(void* s, uint32_t patch, const float* ray8, double cap, uint
   const Scene& S = *(Scene*)s;
   Ray r = load_ray(ray8);
   Best b = {cap, kNoHit, 0.0, 0.0};
-  Counters c = {0, 0, 0, 0, 0, 0};
+  Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<Split> tr;
   if (ray_valid(r)) intersect_patch(S.patches[patch], patch, r, S.L, b, c, &tr);
   int n = (int)std::min<size_t>(tr.size(), (size_t)max_seq);

@@ -1,0 +1,101 @@
+"""GPU-vs-oracle parity gate (test infrastructure, used by tests and the CPU-baseline leg of bench.py).
+
+A ray matches when both miss, or both hit the same patch with |dt| <= 1e-4 D
+(D = scene diagonal) and |du|, |dv| <= 2^-L.  Otherwise it is a disagreement,
+excused only when the paper's error model explains it:
+  * tie   -- the GPU's leaf is, by the oracle's own FP64 arithmetic, entered
+             within 1e-4 D of the oracle's best distance (several leaves or
+             patches are then correct answers; Sec. 3.3 records the closest box);
+  * seam  -- the two hit points are within 1e-4 D of each other, or a reported
+             (u, v) lies within 2^-L of its patch boundary (shared edges);
+  * graze -- the ray only clips the leaf box the other side reported: its path
+             inside that box is shorter than 1e-4 D (silhouettes).
+The gate: identical hit/miss and patch id on >= 99.99 % of the rays of a class,
+and every disagreement (in hit/miss, patch, t, u or v) excused.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import Scene  # noqa: F401  (type of the oracle scene argument)
+
+NO_HIT = 0xFFFFFFFF
+
+
+def ids_of(h: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(h[:, 1]).view(np.uint32)
+
+
+def _path_in_box(ray, lo, hi):
+    o, d = ray[:3].astype(np.float64), ray[4:7].astype(np.float64)
+    near, far = float(ray[3]), np.inf
+    for a in range(3):
+        if d[a] == 0.0:
+            if o[a] < lo[a] or o[a] > hi[a]:
+                return -np.inf
+            continue
+        t0, t1 = (lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]
+        near, far = max(near, min(t0, t1)), min(far, max(t0, t1))
+    return (far - near) * np.linalg.norm(d)
+
+
+def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: float, leaf_depth: int,
+         min_match: float = 0.9999, label: str = "") -> dict:
+    """Compares GPU hits (N, 4) float32 with oracle hits; returns a report dict."""
+    n = len(rays)
+    gid = ids_of(gpu)
+    oid = ora["id"]
+    tol_t = 1e-4 * diameter
+    tol_uv = 2.0 ** -leaf_depth * (1 + 1e-6)
+    g_hit, o_hit = gid != NO_HIT, oid != NO_HIT
+    gt = gpu[:, 0].astype(np.float64)
+    both_miss = ~g_hit & ~o_hit
+    same = g_hit & o_hit & (gid == oid)
+    close = same & (np.abs(gt - ora["t"]) <= tol_t) & (np.abs(gpu[:, 2] - ora["u"]) <= tol_uv) & \
+        (np.abs(gpu[:, 3] - ora["v"]) <= tol_uv)
+    match = both_miss | close
+    kinds = {"tie": 0, "seam": 0, "graze": 0, "hard": 0}
+    hard = []
+    for k in np.where(~match)[0]:
+        ray = rays[k]
+        kind = "hard"
+        if g_hit[k]:
+            e = osc.leaf_entry(gid[k], ray, gpu[k, 2], gpu[k, 3])
+            best_o = ora["t"][k] if o_hit[k] else np.inf
+            if np.isfinite(e) and abs(e - gt[k]) <= tol_t and e <= best_o + tol_t:
+                kind = "tie"
+        if kind == "hard" and g_hit[k] and o_hit[k]:
+            o64, d64 = ray[:3].astype(np.float64), ray[4:7].astype(np.float64)
+            xg, xo = o64 + gt[k] * d64, o64 + ora["t"][k] * d64
+            m = 2.0 ** -leaf_depth
+            near_edge = lambda u, v: min(u, v, 1 - u, 1 - v) <= m * (1 + 1e-6)
+            if np.linalg.norm(xg - xo) <= tol_t or near_edge(gpu[k, 2], gpu[k, 3]) or \
+                    near_edge(ora["u"][k], ora["v"][k]):
+                kind = "seam"
+        if kind == "hard":
+            # the side that hit: does the ray merely clip its leaf box?
+            for side_hit, pid, u, v in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k]),
+                                        (g_hit[k], gid[k], gpu[k, 2], gpu[k, 3])):
+                if side_hit:
+                    lo, hi = osc.leaf_box(pid, u, v)
+                    if _path_in_box(ray, lo, hi) <= tol_t:
+                        kind = "graze"
+                        break
+        kinds[kind] += 1
+        if kind == "hard" and len(hard) < 10:
+            hard.append(dict(ray=int(k), gpu=(float(gt[k]), int(gid[k]), float(gpu[k, 2]), float(gpu[k, 3])),
+                             oracle=(float(ora["t"][k]), int(oid[k]), float(ora["u"][k]), float(ora["v"][k]))))
+    rate = float(match.mean()) if n else 1.0
+    id_rate = float((both_miss | same).mean()) if n else 1.0
+    return dict(label=label, n=n, match=int(match.sum()), match_rate=rate, id_rate=id_rate,
+                hits=int(g_hit.sum()), oracle_hits=int(o_hit.sum()), excused=kinds, hard=hard,
+                ok=(kinds["hard"] == 0 and id_rate >= min_match))
+
+
+def assert_gate(rep: dict, min_match: float = 0.9999):
+    msg = (f"{rep['label']}: strict match {rep['match']}/{rep['n']} ({rep['match_rate']:.6f}), "
+           f"same hit/miss+patch {rep['id_rate']:.6f}, hits gpu/oracle {rep['hits']}/{rep['oracle_hits']}, "
+           f"excused {rep['excused']}, hard examples {rep['hard']}")
+    print(msg, flush=True)
+    assert rep["excused"]["hard"] == 0, msg
+    assert rep["id_rate"] >= min_match, msg

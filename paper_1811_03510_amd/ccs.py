@@ -1,0 +1,187 @@
+"""Python binding of libccs (include/ccs.h): argument marshalling only.
+
+Every step of the intersection runs in the HIP library; PyTorch provides device
+memory and the current stream.  Importing works without a GPU (the library
+loads), but building a scene needs a gfx950 device.  If the library has not been
+built, ``lib()`` raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccs.so")
+
+CCS_OK, CCS_ERR_INVALID_ARG, CCS_ERR_OOM, CCS_ERR_HIP, CCS_ERR_UNSUPPORTED = range(5)
+CCS_BEZIER, CCS_GREGORY = 0, 1
+CCS_HOST, CCS_DEVICE = 0, 1
+NO_HIT = 0xFFFFFFFF
+COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
+
+EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_counted", "ccs_bounce",
+           "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error")
+
+
+class CcsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ccs status {status}: {message}")
+        self.status = status
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("control_points", C.c_void_p), ("patch_types", C.c_void_p), ("n_patches", C.c_uint32),
+                ("location", C.c_int32), ("leaf_depth", C.c_uint32), ("flags", C.c_uint32),
+                ("stream", C.c_void_p)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_patches", C.c_uint32), ("n_nodes", C.c_uint32), ("leaf_depth", C.c_uint32),
+                ("bvh_depth", C.c_uint32), ("device_bytes", C.c_uint64), ("lo", C.c_float * 3),
+                ("hi", C.c_float * 3), ("build_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libccs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python paper_1811_03510_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, u32, i32 = C.c_void_p, C.c_uint32, C.c_int32
+        L.ccs_scene_create.argtypes = [C.POINTER(SceneDesc), C.POINTER(vp)]
+        L.ccs_refit.argtypes = [vp, vp, i32, vp]
+        L.ccs_intersect.argtypes = [vp, vp, u32, vp, vp]
+        L.ccs_intersect_counted.argtypes = [vp, vp, u32, vp, vp, vp]
+        L.ccs_bounce.argtypes = [vp, vp, vp, vp, u32, vp, vp]
+        L.ccs_scene_info_get.argtypes = [vp, C.POINTER(SceneInfo)]
+        L.ccs_scene_destroy.argtypes = [vp]
+        L.ccs_scene_destroy.restype = None
+        L.ccs_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("ccs_scene_destroy", "ccs_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != CCS_OK:
+        raise CcsError(status, lib().ccs_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Scene:
+    """A patch scene on the current GPU.
+
+    control_points: (n, 20, 3) float32 (torch tensor on cuda or cpu, or numpy);
+    patch_types: (n,) uint8 (0 Bezier, 1 Gregory); leaf_depth: L in [1, 16].
+    """
+
+    def __init__(self, control_points, patch_types, leaf_depth: int, stream=None):
+        import torch
+        cp = torch.as_tensor(control_points)
+        ty = torch.as_tensor(patch_types)
+        if cp.dtype != torch.float32 or ty.dtype != torch.uint8:
+            raise TypeError("control_points must be float32 and patch_types uint8")
+        cp = cp.reshape(-1, 20, 3).contiguous()
+        ty = ty.reshape(-1).contiguous()
+        if cp.shape[0] != ty.shape[0]:
+            raise ValueError("control_points and patch_types disagree on the patch count")
+        on_dev = cp.is_cuda
+        if ty.is_cuda != on_dev:
+            ty = ty.to(cp.device)
+        self.n = int(cp.shape[0])
+        self.leaf_depth = int(leaf_depth)
+        desc = SceneDesc(cp.data_ptr() if self.n else None, ty.data_ptr() if self.n else None, self.n,
+                         CCS_DEVICE if on_dev else CCS_HOST, self.leaf_depth, 0,
+                         _stream(stream).value if on_dev else None)
+        h = C.c_void_p()
+        _check(lib().ccs_scene_create(C.byref(desc), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ccs_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = SceneInfo()
+        _check(lib().ccs_scene_info_get(self._h, C.byref(i)))
+        return dict(n_patches=i.n_patches, n_nodes=i.n_nodes, leaf_depth=i.leaf_depth, bvh_depth=i.bvh_depth,
+                    device_bytes=int(i.device_bytes), lo=list(i.lo), hi=list(i.hi),
+                    build_seconds=i.build_seconds)
+
+    @staticmethod
+    def _rays(rays):
+        import torch
+        r = torch.as_tensor(rays)
+        if not r.is_cuda or r.dtype != torch.float32 or r.shape[-1] != 8 or not r.is_contiguous():
+            raise ValueError("rays must be a contiguous (N, 8) float32 CUDA tensor")
+        return r
+
+    def intersect(self, rays, hits=None, stream=None):
+        """Closest hits (N, 4) float32 {t, patch id bits, u, v}; ``hits_ids(h)`` reads the ids."""
+        import torch
+        r = self._rays(rays)
+        n = r.shape[0]
+        if hits is None:
+            hits = torch.empty((n, 4), dtype=torch.float32, device=r.device)
+        _check(lib().ccs_intersect(self._h, _ptr(r), n, _ptr(hits), _stream(stream)))
+        return hits
+
+    def intersect_counted(self, rays, stream=None):
+        import torch
+        r = self._rays(rays)
+        n = r.shape[0]
+        hits = torch.empty((n, 4), dtype=torch.float32, device=r.device)
+        cnt = torch.empty((n, 8), dtype=torch.int32, device=r.device)
+        _check(lib().ccs_intersect_counted(self._h, _ptr(r), n, _ptr(hits), _ptr(cnt), _stream(stream)))
+        return hits, cnt
+
+    def refit(self, control_points, stream=None):
+        import torch
+        cp = torch.as_tensor(control_points)
+        if cp.dtype != torch.float32 or cp.numel() != self.n * 60:
+            raise ValueError("refit input must be float32 with n x 20 x 3 values")
+        cp = cp.contiguous()
+        self._refit_keep = cp  # device input must outlive the queued work
+        _check(lib().ccs_refit(self._h, _ptr(cp), CCS_DEVICE if cp.is_cuda else CCS_HOST, _stream(stream)))
+
+    def bounce(self, rays, hits, uniforms, out=None, stream=None):
+        import torch
+        r = self._rays(rays)
+        n = r.shape[0]
+        if out is None:
+            out = torch.empty_like(r)
+        _check(lib().ccs_bounce(self._h, _ptr(r), _ptr(hits.contiguous()), _ptr(uniforms.contiguous()), n,
+                                _ptr(out), _stream(stream)))
+        return out
+
+
+def hit_ids(hits) -> np.ndarray:
+    """Patch ids of a hits tensor/array as uint32 (CCS_NO_HIT for misses)."""
+    h = hits.detach().cpu().numpy() if hasattr(hits, "detach") else np.asarray(hits)
+    return np.ascontiguousarray(h[:, 1]).view(np.uint32)

@@ -1,0 +1,329 @@
+// C ABI of the intersector: validation, scene build and upload, launches.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ccs.h"
+#include "bvh_build.h"
+#include "ccs_internal.h"
+#include "patch_math.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+ccs_status fail(ccs_status s, const std::string& msg) {
+  g_error = msg;
+  return s;
+}
+
+ccs_status hip_fail(hipError_t e, const char* what) {
+  return fail(CCS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kTraversalStack = 48;  // matches the LDS stack of the intersect kernel
+
+}  // namespace
+
+struct ccs_scene {
+  ccs::DeviceScene dev{};
+  int device = 0;
+  uint32_t bvh_depth = 0;
+  uint64_t device_bytes = 0;
+  float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  double build_seconds = 0.0;
+  float* cp_stage = nullptr;  // device staging buffer for host refit input
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+template <class T>
+ccs_status dev_alloc(ccs_scene* s, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CCS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  s->allocations.push_back(q);
+  s->device_bytes += count * sizeof(T);
+  *p = static_cast<T*>(q);
+  return CCS_OK;
+}
+
+void free_scene(ccs_scene* s) {
+  if (!s) return;
+  for (void* p : s->allocations) (void)hipFree(p);
+  delete s;
+}
+
+bool is_gfx950(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+// Host copies of the caller's control points and tags (device input is fetched).
+ccs_status fetch_inputs(const ccs_scene_desc* d, std::vector<float>& cp, std::vector<uint8_t>& types) {
+  const size_t n = d->n_patches;
+  cp.resize(n * 60);
+  types.resize(n);
+  if (n == 0) return CCS_OK;
+  if (d->location == CCS_HOST) {
+    std::memcpy(cp.data(), d->control_points, n * 60 * sizeof(float));
+    std::memcpy(types.data(), d->patch_types, n);
+    return CCS_OK;
+  }
+  hipError_t e = hipMemcpy(cp.data(), d->control_points, n * 60 * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(types.data(), d->patch_types, n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "copying scene input to the host");
+  return CCS_OK;
+}
+
+ccs_status check_finite(const float* cp, size_t count) {
+  for (size_t k = 0; k < count; ++k)
+    if (!std::isfinite(cp[k])) return fail(CCS_ERR_INVALID_ARG, "control point value " + std::to_string(k) + " is not finite");
+  return CCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ccs_last_error(void) { return g_error.c_str(); }
+
+ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
+  g_error.clear();
+  if (!out) return fail(CCS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(CCS_ERR_INVALID_ARG, "desc is NULL");
+  const uint32_t n = desc->n_patches;
+  if (n > 0 && (!desc->control_points || !desc->patch_types))
+    return fail(CCS_ERR_INVALID_ARG, "control_points or patch_types is NULL");
+  if (n >= (1u << 31)) return fail(CCS_ERR_INVALID_ARG, "n_patches must be below 2^31");
+  if (desc->leaf_depth < 1 || desc->leaf_depth > CCS_MAX_LEAF_DEPTH)
+    return fail(CCS_ERR_INVALID_ARG, "leaf_depth must be in [1, 16]");
+  if (desc->location != CCS_HOST && desc->location != CCS_DEVICE)
+    return fail(CCS_ERR_INVALID_ARG, "location must be CCS_HOST or CCS_DEVICE");
+  if (desc->flags != 0) return fail(CCS_ERR_UNSUPPORTED, "flags must be 0");
+
+  // host-side validation needs no GPU; device input is fetched first
+  std::vector<float> cp;
+  std::vector<uint8_t> types;
+  if (desc->location == CCS_HOST) {
+    for (uint32_t k = 0; k < n; ++k)
+      if (desc->patch_types[k] > 1) return fail(CCS_ERR_INVALID_ARG, "patch type " + std::to_string(k) + " is not 0 or 1");
+    ccs_status st = check_finite(desc->control_points, (size_t)n * 60);
+    if (st != CCS_OK) return st;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (!is_gfx950(dev)) return fail(CCS_ERR_UNSUPPORTED, "the current device is not gfx950");
+  ccs_status st = fetch_inputs(desc, cp, types);
+  if (st != CCS_OK) return st;
+  if (desc->location == CCS_DEVICE) {
+    for (uint32_t k = 0; k < n; ++k)
+      if (types[k] > 1) return fail(CCS_ERR_INVALID_ARG, "patch type " + std::to_string(k) + " is not 0 or 1");
+    st = check_finite(cp.data(), cp.size());
+    if (st != CCS_OK) return st;
+  }
+
+  const auto t0 = std::chrono::steady_clock::now();
+  // patch boxes (hull of 16 or 20 points) and fp32 anchors (box centres)
+  std::vector<ccs::BuildBox> boxes(n);
+  for (uint32_t k = 0; k < n; ++k) {
+    const float* p = cp.data() + 60 * (size_t)k;
+    const int np = types[k] == CCS_GREGORY ? 20 : 16;
+    ccs::BuildBox& b = boxes[k];
+    for (int a = 0; a < 3; ++a) b.lo[a] = b.hi[a] = p[a];
+    for (int s = 1; s < np; ++s)
+      for (int a = 0; a < 3; ++a) {
+        b.lo[a] = std::fmin(b.lo[a], p[3 * s + a]);
+        b.hi[a] = std::fmax(b.hi[a], p[3 * s + a]);
+      }
+  }
+  uint32_t log2n = 0;
+  while ((1ull << log2n) < (uint64_t)std::max<uint32_t>(n, 1)) ++log2n;
+  const uint32_t sah_depth = (uint32_t)std::max<int>(8, kTraversalStack - 1 - (int)log2n);
+  const int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  ccs::BvhOutput bvh = ccs::build_bvh(boxes, sah_depth, threads);
+  if (n > 0 && bvh.max_depth >= (uint32_t)kTraversalStack)
+    return fail(CCS_ERR_UNSUPPORTED, "BVH deeper than the traversal stack");
+
+  // records in leaf order
+  std::vector<float> recs((size_t)n * ccs::kRecFloats, 0.0f);
+  std::vector<uint32_t> inv_perm(n);
+  ccs_scene* s = new ccs_scene();
+  for (int a = 0; a < 3; ++a) {
+    s->lo[a] = n ? INFINITY : 0.0f;
+    s->hi[a] = n ? -INFINITY : 0.0f;
+  }
+  for (uint32_t r = 0; r < n; ++r) {
+    const uint32_t k = bvh.perm[r];
+    inv_perm[k] = r;
+    const float* p = cp.data() + 60 * (size_t)k;
+    float* q = recs.data() + (size_t)r * ccs::kRecFloats;
+    const ccs::BuildBox& b = boxes[k];
+    float anc[3];
+    for (int a = 0; a < 3; ++a) {
+      anc[a] = 0.5f * (b.lo[a] + b.hi[a]);
+      s->lo[a] = std::fmin(s->lo[a], b.lo[a]);
+      s->hi[a] = std::fmax(s->hi[a], b.hi[a]);
+    }
+    for (int sl = 0; sl < 16; ++sl)
+      for (int a = 0; a < 3; ++a) q[16 * a + sl] = p[3 * sl + a] - anc[a];
+    for (int sl = 16; sl < 20; ++sl)
+      for (int a = 0; a < 3; ++a) q[48 + 4 * a + (sl - 16)] = p[3 * sl + a] - anc[a];
+    q[60] = anc[0];
+    q[61] = anc[1];
+    q[62] = anc[2];
+    uint32_t meta = k | (types[k] == CCS_GREGORY ? ccs::kGregoryBit : 0u);
+    std::memcpy(q + 63, &meta, 4);
+  }
+  s->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  s->device = dev;
+  s->bvh_depth = bvh.max_depth;
+  const uint32_t n_nodes = n ? (uint32_t)(bvh.nodes.size() / 16) : 0;
+  ccs::DeviceScene& D = s->dev;
+  D.n_patches = n;
+  D.n_nodes = n_nodes;
+  D.leaf_depth = (int)desc->leaf_depth;
+  float4* nodes = nullptr;
+  uint32_t *perm = nullptr, *invp = nullptr, *arr = nullptr;
+  int32_t *lpar = nullptr, *npar = nullptr;
+  float* drec = nullptr;
+  if ((st = dev_alloc(s, &nodes, (size_t)n_nodes * 4)) != CCS_OK || (st = dev_alloc(s, &drec, recs.size())) != CCS_OK ||
+      (st = dev_alloc(s, &perm, n)) != CCS_OK || (st = dev_alloc(s, &invp, n)) != CCS_OK ||
+      (st = dev_alloc(s, &lpar, n)) != CCS_OK || (st = dev_alloc(s, &npar, n_nodes)) != CCS_OK ||
+      (st = dev_alloc(s, &arr, n_nodes)) != CCS_OK) {
+    free_scene(s);
+    return st;
+  }
+  hipStream_t stream = (hipStream_t)desc->stream;
+  struct Up {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  } ups[] = {{nodes, bvh.nodes.data(), bvh.nodes.size() * sizeof(float)},
+             {drec, recs.data(), recs.size() * sizeof(float)},
+             {perm, bvh.perm.data(), (size_t)n * 4},
+             {invp, inv_perm.data(), (size_t)n * 4},
+             {lpar, bvh.leaf_parent.data(), (size_t)n * 4},
+             {npar, bvh.node_parent.data(), (size_t)n_nodes * 4}};
+  for (const Up& u : ups) {
+    if (u.bytes == 0) continue;
+    e = hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+      free_scene(s);
+      return hip_fail(e, "uploading the scene");
+    }
+  }
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    free_scene(s);
+    return hip_fail(e, "synchronizing the scene upload");
+  }
+  D.nodes = nodes;
+  D.recs = drec;
+  D.perm = perm;
+  D.inv_perm = invp;
+  D.leaf_parent = lpar;
+  D.node_parent = npar;
+  D.arrivals = arr;
+  *out = s;
+  return CCS_OK;
+}
+
+ccs_status ccs_refit(ccs_scene* s, const float* control_points, int32_t location, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (s->dev.n_patches == 0) return CCS_OK;
+  if (!control_points) return fail(CCS_ERR_INVALID_ARG, "control_points is NULL");
+  if (location != CCS_HOST && location != CCS_DEVICE)
+    return fail(CCS_ERR_INVALID_ARG, "location must be CCS_HOST or CCS_DEVICE");
+  const size_t count = (size_t)s->dev.n_patches * 60;
+  hipStream_t st = (hipStream_t)stream;
+  const float* src = control_points;
+  if (location == CCS_HOST) {
+    ccs_status c = check_finite(control_points, count);
+    if (c != CCS_OK) return c;
+    if (!s->cp_stage) {
+      c = dev_alloc(s, &s->cp_stage, count);
+      if (c != CCS_OK) return c;
+    }
+    hipError_t e = hipMemcpyAsync(s->cp_stage, control_points, count * sizeof(float), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "copying refit input");
+    src = s->cp_stage;
+  }
+  hipError_t e = ccs::launch_refit(s->dev, src, st);
+  if (e != hipSuccess) return hip_fail(e, "refit launch");
+  return CCS_OK;
+}
+
+ccs_status ccs_intersect(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (n == 0) return CCS_OK;
+  if (!rays || !hits) return fail(CCS_ERR_INVALID_ARG, "rays or hits is NULL");
+  hipError_t e = ccs::launch_intersect(s->dev, rays, n, hits, nullptr, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "intersect launch");
+  return CCS_OK;
+}
+
+ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
+                                 uint32_t* counters, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (n == 0) return CCS_OK;
+  if (!rays || !hits || !counters) return fail(CCS_ERR_INVALID_ARG, "rays, hits or counters is NULL");
+  hipError_t e = ccs::launch_intersect(s->dev, rays, n, hits, counters, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "intersect launch");
+  return CCS_OK;
+}
+
+ccs_status ccs_bounce(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms, uint32_t n,
+                      ccs_ray* out_rays, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (n == 0) return CCS_OK;
+  if (!rays || !hits || !uniforms || !out_rays) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if ((const void*)out_rays == (const void*)rays) return fail(CCS_ERR_INVALID_ARG, "out_rays aliases rays");
+  hipError_t e = ccs::launch_bounce(s->dev, rays, hits, uniforms, n, out_rays, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "bounce launch");
+  return CCS_OK;
+}
+
+ccs_status ccs_scene_info_get(const ccs_scene* s, ccs_scene_info* info) {
+  g_error.clear();
+  if (!s || !info) return fail(CCS_ERR_INVALID_ARG, "scene or info is NULL");
+  info->n_patches = s->dev.n_patches;
+  info->n_nodes = s->dev.n_nodes;
+  info->leaf_depth = (uint32_t)s->dev.leaf_depth;
+  info->bvh_depth = s->bvh_depth;
+  info->device_bytes = s->device_bytes;
+  for (int a = 0; a < 3; ++a) {
+    info->lo[a] = s->lo[a];
+    info->hi[a] = s->hi[a];
+  }
+  info->build_seconds = s->build_seconds;
+  return CCS_OK;
+}
+
+void ccs_scene_destroy(ccs_scene* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_scene(s);
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ccs.h"
+
+namespace ccs {
+
+// BVH node: 64 bytes = 4 float4.
+//   f[0] = (lo0.x, lo0.y, lo0.z, hi0.x)
+//   f[1] = (hi0.y, hi0.z, lo1.x, lo1.y)
+//   f[2] = (lo1.z, hi1.x, hi1.y, hi1.z)
+//   f[3] = (child0, child1, -, -) as int bits: >= 0 internal node, < 0 patch
+//          record ~child (one patch per leaf).  An empty child has lo > hi.
+struct DeviceScene {
+  const float4* nodes;
+  float* recs;               // n x kRecFloats
+  uint32_t n_patches;
+  uint32_t n_nodes;
+  int leaf_depth;
+  const uint32_t* perm;      // record -> original index
+  const uint32_t* inv_perm;  // original index -> record
+  const int32_t* leaf_parent;  // record -> (node << 1 | side)
+  const int32_t* node_parent;  // node -> (parent << 1 | side), -1 for the root
+  uint32_t* arrivals;        // n_nodes counters for the bottom-up refit
+};
+
+hipError_t launch_intersect(const DeviceScene& s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, uint32_t* counters,
+                            hipStream_t stream);
+hipError_t launch_refit(const DeviceScene& s, const float* cp_world, hipStream_t stream);
+hipError_t launch_bounce(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
+                         uint32_t n, ccs_ray* out, hipStream_t stream);
+
+}  // namespace ccs

@@ -190,24 +190,32 @@ def _bern(t):
     return np.stack((s * s * s, 3 * t * s * s, 3 * t * t * s, t * t * t), axis=-1)
 
 
-def surface_points(cp: np.ndarray, types: np.ndarray, idx: np.ndarray, u: np.ndarray,
-                   v: np.ndarray) -> np.ndarray:
-    """Surface points of patches ``idx`` at (u, v), float64 (the patch definition of Sec. 2)."""
+def _blended_grids(cp: np.ndarray, types: np.ndarray, idx: np.ndarray):
     g = cp[idx].astype(np.float64)
-    grid = g[:, :16].copy()
-    greg = types[idx] == GREGORY
+    return g, types[idx] == GREGORY
+
+
+def _eval_gathered(g: np.ndarray, greg: np.ndarray, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    grid = g[:, :16]
     if np.any(greg):
+        grid = grid.copy()
         for k, (slot, pv) in enumerate(zip(INNER_SLOTS, PV_SLOTS)):
             i, j = (1 if k % 2 == 0 else 2), (1 if k < 2 else 2)
-            du = u if i == 1 else 1.0 - u
-            dv = v if j == 1 else 1.0 - v
+            du = u[greg] if i == 1 else 1.0 - u[greg]
+            dv = v[greg] if j == 1 else 1.0 - v[greg]
             den = du + dv
             lam = np.where(den > 0, du / np.where(den > 0, den, 1.0), 0.5)
-            blend = lam[:, None] * g[:, slot] + (1.0 - lam[:, None]) * g[:, pv]
-            grid[greg, slot] = blend[greg]
+            grid[greg, slot] = lam[:, None] * g[greg, slot] + (1.0 - lam[:, None]) * g[greg, pv]
     bu, bv = _bern(u), _bern(v)
     w = (bv[:, :, None] * bu[:, None, :]).reshape(-1, 16)  # slot 4*j + i
     return np.einsum("ns,nsc->nc", w, grid)
+
+
+def surface_points(cp: np.ndarray, types: np.ndarray, idx: np.ndarray, u: np.ndarray,
+                   v: np.ndarray) -> np.ndarray:
+    """Surface points of patches ``idx`` at (u, v), float64 (the patch definition of Sec. 2)."""
+    g, greg = _blended_grids(cp, types, idx)
+    return _eval_gathered(g, greg, np.asarray(u, np.float64), np.asarray(v, np.float64))
 
 
 def onb(n: np.ndarray):
@@ -230,7 +238,7 @@ def cosine_dirs(n: np.ndarray, u1: np.ndarray, u2: np.ndarray) -> np.ndarray:
 
 
 def surface_bounce_rays(cp: np.ndarray, types: np.ndarray, leaf_depth: int, eye, n: int,
-                        seed: int = STREAM_BOUNCE) -> np.ndarray:
+                        seed: int = STREAM_BOUNCE, chunk: int = 1 << 16) -> np.ndarray:
     """Secondary-ray stand-in: one cosine-weighted bounce from n seeded surface points.
 
     A patch is drawn uniformly, (u, v) uniformly in [0.01, 0.99]^2; the normal is
@@ -240,27 +248,31 @@ def surface_bounce_rays(cp: np.ndarray, types: np.ndarray, leaf_depth: int, eye,
     """
     npatch = cp.shape[0]
     s = [substream(seed, k) for k in range(5)]
-    idx = np.minimum((uniform(s[0], n) * npatch).astype(np.int64), npatch - 1)
-    u = 0.01 + 0.98 * uniform(s[1], n)
-    v = 0.01 + 0.98 * uniform(s[2], n)
+    idx_all = np.minimum((uniform(s[0], n) * npatch).astype(np.int64), npatch - 1)
+    u_all = 0.01 + 0.98 * uniform(s[1], n)
+    v_all = 0.01 + 0.98 * uniform(s[2], n)
+    w1_all, w2_all = uniform(s[3], n), uniform(s[4], n)
+    out = np.zeros((n, 8), dtype=np.float32)
+    eye = np.asarray(eye, dtype=np.float64)
     h = 1e-6
-    x = surface_points(cp, types, idx, u, v)
-    fu = surface_points(cp, types, idx, u + h, v) - surface_points(cp, types, idx, u - h, v)
-    fv = surface_points(cp, types, idx, u, v + h) - surface_points(cp, types, idx, u, v - h)
-    nrm = np.cross(fu, fv)
-    nrm /= np.linalg.norm(nrm, axis=-1, keepdims=True)
-    toward = np.asarray(eye, dtype=np.float64)[None, :] - x
-    nrm *= np.where(np.sum(nrm * toward, axis=-1) < 0, -1.0, 1.0)[:, None]
-    c = cp[idx].astype(np.float64)
-    ext = (c.max(axis=1) - c.min(axis=1)).sum(axis=-1)
-    o = x + (ext * 2.0 ** -leaf_depth)[:, None] * nrm
-    d = cosine_dirs(nrm, uniform(s[3], n), uniform(s[4], n))
-    d /= np.linalg.norm(d, axis=-1, keepdims=True)
-    out = np.zeros((n, 8), dtype=np.float64)
-    out[:, 0:3] = o
-    out[:, 4:7] = d
+    for b in range(0, n, chunk):
+        e = min(n, b + chunk)
+        idx, u, v = idx_all[b:e], u_all[b:e], v_all[b:e]
+        g, greg = _blended_grids(cp, types, idx)
+        x = _eval_gathered(g, greg, u, v)
+        fu = _eval_gathered(g, greg, u + h, v) - _eval_gathered(g, greg, u - h, v)
+        fv = _eval_gathered(g, greg, u, v + h) - _eval_gathered(g, greg, u, v - h)
+        nrm = np.cross(fu, fv)
+        nrm /= np.linalg.norm(nrm, axis=-1, keepdims=True)
+        nrm *= np.where(np.sum(nrm * (eye[None, :] - x), axis=-1) < 0, -1.0, 1.0)[:, None]
+        ext = (g.max(axis=1) - g.min(axis=1)).sum(axis=-1)
+        o = x + (ext * 2.0 ** -leaf_depth)[:, None] * nrm
+        d = cosine_dirs(nrm, w1_all[b:e], w2_all[b:e])
+        d /= np.linalg.norm(d, axis=-1, keepdims=True)
+        out[b:e, 0:3] = o
+        out[b:e, 4:7] = d
     out[:, 7] = np.inf
-    return out.astype(np.float32)
+    return out
 
 
 # ------------------------------------------------------------------------ configs
@@ -334,10 +346,13 @@ def instanced_scene(n_objects: int = 2000, n_theta: int = 25, n_phi: int = 20,
     nz = normal(substream(STREAM_SCENE, 1), n_objects * n_theta * n_phi)
     cages = cages + nrm[None] * (noise * nz).reshape(n_objects, n_theta, n_phi, 1)
     rot = quat_rot(q)
-    cages = np.einsum("oab,otpb->otpa", rot, cages) * scale[:, None, None, None] \
-        + centre[:, None, None, :]
-    grids = bspline_to_bezier(cages).reshape(-1, 16, 3)
-    cp = to_twenty(grids)
+    per = n_theta * n_phi
+    cp = np.empty((n_objects * per, 20, 3), dtype=np.float64)
+    for b in range(0, n_objects, 128):  # object chunks keep the temporaries cache-sized
+        e = min(n_objects, b + 128)
+        cg = np.einsum("oab,otpb->otpa", rot[b:e], cages[b:e]) * scale[b:e, None, None, None] \
+            + centre[b:e, None, None, :]
+        cp[b * per:e * per] = to_twenty(bspline_to_bezier(cg).reshape(-1, 16, 3))
     n = cp.shape[0]
     types = np.zeros(n, dtype=np.uint8)
     sel = choose(STREAM_GREGORY_CHOICE, n, int(round(gregory_frac * n)))

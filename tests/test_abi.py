@@ -1,0 +1,92 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry point,
+and validates arguments on the host before any HIP call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1811_03510_amd import ccs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ccs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 8
+    lib = ccs.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(ccs.EXPORTS)
+
+
+def test_struct_layouts():
+    class Ray(C.Structure):
+        _fields_ = [(f, C.c_float) for f in ("ox", "oy", "oz", "tmin", "dx", "dy", "dz", "tmax")]
+
+    class Hit(C.Structure):
+        _fields_ = [("t", C.c_float), ("patch_id", C.c_uint32), ("u", C.c_float), ("v", C.c_float)]
+    assert C.sizeof(Ray) == 32 and C.sizeof(Hit) == 16
+    assert C.sizeof(ccs.SceneDesc) == 40
+
+
+def create(desc):
+    h = C.c_void_p()
+    st = ccs.lib().ccs_scene_create(C.byref(desc) if desc is not None else None, C.byref(h))
+    return st, ccs.lib().ccs_last_error().decode(), h
+
+
+def host_desc(cp, ty, L=12, flags=0, location=ccs.CCS_HOST):
+    return ccs.SceneDesc(cp.ctypes.data if cp is not None else None, ty.ctypes.data if ty is not None else None,
+                         len(ty) if ty is not None else 3, location, L, flags, None)
+
+
+def test_host_validation_errors():
+    cp = np.zeros((3, 20, 3), np.float32)
+    ty = np.zeros(3, np.uint8)
+    st, msg, _ = create(None)
+    assert st == ccs.CCS_ERR_INVALID_ARG and "desc" in msg
+    assert ccs.lib().ccs_scene_create(C.byref(host_desc(cp, ty)), None) == ccs.CCS_ERR_INVALID_ARG
+    st, msg, h = create(host_desc(None, ty))
+    assert st == ccs.CCS_ERR_INVALID_ARG and h.value is None
+    for L in (0, 17, 100):
+        st, msg, _ = create(host_desc(cp, ty, L=L))
+        assert st == ccs.CCS_ERR_INVALID_ARG and "leaf_depth" in msg
+    bad = ty.copy()
+    bad[1] = 2
+    st, msg, _ = create(host_desc(cp, bad))
+    assert st == ccs.CCS_ERR_INVALID_ARG and "type" in msg
+    for v in (np.nan, np.inf, -np.inf):
+        c2 = cp.copy()
+        c2[2, 7, 1] = v
+        st, msg, _ = create(host_desc(c2, ty))
+        assert st == ccs.CCS_ERR_INVALID_ARG and "finite" in msg
+    st, msg, _ = create(host_desc(cp, ty, flags=1))
+    assert st == ccs.CCS_ERR_UNSUPPORTED
+    st, msg, _ = create(host_desc(cp, ty, location=7))
+    assert st == ccs.CCS_ERR_INVALID_ARG
+
+
+def test_null_scene_calls_fail_cleanly():
+    L = ccs.lib()
+    assert L.ccs_intersect(None, None, 0, None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_refit(None, None, 0, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_bounce(None, None, None, None, 4, None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_intersect_counted(None, None, 1, None, None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_scene_info_get(None, None) == ccs.CCS_ERR_INVALID_ARG
+    L.ccs_scene_destroy(None)
+    assert "NULL" in L.ccs_last_error().decode()
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    monkeypatch.setattr(ccs, "_lib", None)
+    monkeypatch.setattr(ccs, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libccs.so"))
+    with pytest.raises(ImportError):
+        ccs.lib()

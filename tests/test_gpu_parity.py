@@ -1,0 +1,218 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the
+same seeded inputs, at sizes spanning many waves with ragged tails, and at the
+full 1M-patch / 1920x1080 size on a seeded sample of rays."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1811_03510_amd import scenes as S
+
+from oracle.parity import assert_gate, gate, ids_of
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ccs():
+    from paper_1811_03510_amd import ccs as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def c1_gpu(ccs, c1):
+    _say("building the 512-patch torus scene on the GPU")
+    return ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+
+
+def run(scene, rays_np):
+    r = torch.from_numpy(np.ascontiguousarray(rays_np, dtype=np.float32)).cuda()
+    h = scene.intersect(r)
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+@pytest.mark.parametrize("cls", ["primary", "diffuse"])
+def test_torus512_all_rays(ccs, c1, c1_oracle, c1_gpu, cls):
+    rays = c1.primary if cls == "primary" else c1.diffuse
+    _say(f"torus512 {cls}: {len(rays)} rays")
+    g = run(c1_gpu, rays)
+    o = c1_oracle.intersect(rays)
+    assert_gate(gate(g, o, rays, c1_oracle, c1.diameter, c1.leaf_depth, label=f"torus512-{cls}"))
+
+
+def test_ragged_launches_are_bitwise_identical(ccs, c1, c1_gpu):
+    """Per-ray results do not depend on the launch size or the ray's position in it."""
+    rays = c1.diffuse
+    full = run(c1_gpu, rays)
+    rng = np.random.default_rng(3)
+    for n in (1, 63, 64, 65, 1000, 4097):
+        idx = rng.choice(len(rays), size=n, replace=False)
+        _say(f"ragged launch of {n} rays")
+        part = run(c1_gpu, rays[idx])
+        assert np.array_equal(part.view(np.uint32), full[idx].view(np.uint32)), n
+
+
+def test_counted_kernel_gives_the_same_hits(ccs, c1, c1_gpu, c1_oracle):
+    r = torch.from_numpy(c1.primary).cuda()
+    h0 = c1_gpu.intersect(r)
+    h1, cnt = c1_gpu.intersect_counted(r)
+    torch.cuda.synchronize()
+    h0, h1, cnt = h0.cpu().numpy(), h1.cpu().numpy(), cnt.cpu().numpy().astype(np.int64)
+    assert np.array_equal(h0.view(np.uint32), h1.view(np.uint32))
+    hit = ids_of(h1) != O.NO_HIT
+    L = c1.leaf_depth
+    assert np.all(cnt[hit, 2] >= 2 * L) and np.all(cnt[hit, 5] >= 1) and np.all(cnt[~hit, 5] == 0)
+    # same algorithm: totals of the per-patch work agree with the oracle's to a few percent
+    oc = c1_oracle.intersect(c1.primary, counters=True)["counters"].astype(np.int64)
+    for k in (2, 3, 4, 5, 6, 7):
+        a, b = cnt[:, k].sum(), oc[:, k].sum()
+        assert abs(a - b) <= 0.05 * max(a, b) + 10, (k, a, b)
+
+
+def test_empty_inputs(ccs, c1, c1_gpu):
+    r = torch.zeros((0, 8), dtype=torch.float32, device="cuda")
+    h = c1_gpu.intersect(r)
+    assert h.shape == (0, 4)
+    empty = ccs.Scene(torch.zeros((0, 20, 3), dtype=torch.float32).cuda(),
+                      torch.zeros((0,), dtype=torch.uint8).cuda(), 12)
+    g = run(empty, c1.primary[:100])
+    assert np.all(ids_of(g) == O.NO_HIT) and np.all(np.isinf(g[:, 0]))
+
+
+def affine_cp(rng):
+    a, e1, e2 = rng.normal(size=3), rng.normal(size=3), rng.normal(size=3)
+    g = np.array([[a + (i / 3) * e1 + (j / 3) * e2 for i in range(4)] for j in range(4)]).reshape(16, 3)
+    return np.concatenate([g, g[[5, 6, 9, 10]]])
+
+
+@pytest.mark.parametrize("L", [1, 4, 12, 16])
+def test_single_patches_and_special_rays(ccs, L):
+    rng = np.random.default_rng(L)
+    for trial in range(4):
+        cp = affine_cp(rng) if trial < 2 else S.config1(8, 8, False).cp[rng.integers(0, 512)].astype(np.float64)
+        cp = cp.astype(np.float32)[None]
+        ty = np.array([trial % 2], np.uint8)
+        osc = O.Scene(cp, ty, L)
+        gsc = ccs.Scene(torch.from_numpy(cp).cuda(), torch.from_numpy(ty).cuda(), L)
+        x = S.surface_points(cp, ty, np.zeros(256, np.int64), rng.uniform(size=256), rng.uniform(size=256))
+        d = rng.normal(size=(256, 3))
+        rays = np.zeros((256 + 6, 8), np.float32)
+        rays[:256, :3], rays[:256, 4:7], rays[:256, 7] = x - 2.0 * d, d, np.inf
+        c = x[0]
+        rays[256:] = [[c[0], c[1], c[2] + 5, 0, 0, 0, -1, np.inf],      # axis-aligned
+                      [c[0], c[1], c[2] + 5, 0, 0, 0, 0, np.inf],       # zero direction
+                      [c[0], c[1], c[2] + 5, 3, 0, 0, -1, 2],           # tmin > tmax
+                      [np.nan, 0, 0, 0, 0, 0, 1, np.inf],               # non-finite origin
+                      [c[0], c[1], c[2], 0, 1, 0, 0, np.inf],           # origin on the surface
+                      [c[0], c[1], c[2] + 5, 0, 0, 0, -1, 0.5]]         # tmax too short
+        _say(f"single patch L={L} trial {trial}")
+        g = run(gsc, rays)
+        o = osc.intersect(rays)
+        diam = float(np.linalg.norm(np.ptp(cp.reshape(-1, 3).astype(np.float64), axis=0)))
+        assert_gate(gate(g, o, rays, osc, diam, L, min_match=0.99, label=f"single-L{L}-{trial}"))
+        assert np.all(ids_of(g)[[257, 258, 259]] == O.NO_HIT)
+
+
+def test_rays_through_shared_edges_never_miss(ccs, c1, c1_gpu):
+    rng = np.random.default_rng(5)
+    nv = 16
+    pts = []
+    for _ in range(4000):
+        i, j = rng.integers(0, 32), rng.integers(0, nv)
+        a = np.array([i * nv + j])
+        kind, s = rng.integers(0, 3), rng.uniform()
+        if kind == 0:
+            x = S.surface_points(c1.cp, c1.types, a, np.array([1.0]), np.array([s]))[0]
+        elif kind == 1:
+            x = S.surface_points(c1.cp, c1.types, a, np.array([s]), np.array([1.0]))[0]
+        else:
+            x = c1.cp[a[0], 15].astype(np.float64)
+        pts.append(x)
+    pts = np.array(pts)
+    o = np.array(c1.eye)[None] + rng.normal(size=(len(pts), 3)) * 0.3
+    d = pts - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.zeros((len(pts), 8), np.float32)
+    rays[:, :3], rays[:, 4:7], rays[:, 7] = o, d, np.inf
+    g = run(c1_gpu, rays)
+    t_target = np.einsum("ij,ij->i", pts - rays[:, :3], rays[:, 4:7].astype(np.float64))
+    missed = ids_of(g) == O.NO_HIT
+    assert missed.sum() == 0, np.where(missed)[0][:10]
+    assert np.all(g[:, 0] <= t_target + 1e-4 * c1.diameter)
+
+
+def test_bounce_matches_oracle(ccs, c1, c1_oracle, c1_gpu):
+    """Secondary rays from the same (ray, hit, uniforms) inputs on both sides."""
+    rng = np.random.default_rng(8)
+    n = 4096
+    idx = rng.integers(0, 512, size=n)
+    L = c1.leaf_depth
+    leaf = 2.0 ** -L
+    u = (rng.integers(0, 1 << L, n) + 0.5) * leaf
+    v = (rng.integers(0, 1 << L, n) + 0.5) * leaf
+    x = S.surface_points(c1.cp, c1.types, idx, u, v)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t = rng.uniform(0.5, 2.0, size=n)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, :3], rays[:, 4:7], rays[:, 7] = x - t[:, None] * d, d, np.inf
+    hits = np.zeros((n, 4), np.float32)
+    hits[:, 0], hits[:, 2], hits[:, 3] = t, u, v
+    hits[:, 1] = idx.astype(np.uint32).view(np.float32)
+    hits[::17, 1] = np.array([O.NO_HIT], np.uint32).view(np.float32)[0]
+    hits[::17, 0] = np.inf
+    w = rng.uniform(size=(n, 2)).astype(np.float32)
+    ref = c1_oracle.bounce(rays, hits, w)
+    out = c1_gpu.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.float64)
+    active = ref[:, 3] <= ref[:, 7]
+    assert np.array_equal(active, out[:, 3] <= out[:, 7])
+    np.testing.assert_allclose(out[active, :3], ref[active, :3], atol=2e-6 * c1.diameter)
+    np.testing.assert_allclose(out[active, 4:7], ref[active, 4:7], atol=2e-5)
+
+
+def test_refit_matches_oracle_on_moved_scene(ccs, c1):
+    """Moving the control points (a smooth displacement field: shared points move
+    together) and refitting gives the oracle's hits on the moved scene; refitting
+    back gives bitwise the original hits."""
+    cp0 = c1.cp.astype(np.float64)
+    x = cp0.reshape(-1, 3)
+    k = np.array([[0.9, 0.3, 0.1], [0.2, -0.7, 0.5], [0.1, 0.4, -0.9]]) * 2 * np.pi
+    disp = 0.01 * np.sin(x @ k.T + np.array([0.3, 1.1, 2.0]))
+    cp1 = (x + disp).reshape(cp0.shape).astype(np.float32)
+    gsc = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+    base = run(gsc, c1.primary)
+    _say("refit to moved control points")
+    gsc.refit(torch.from_numpy(cp1).cuda())
+    g = run(gsc, c1.primary)
+    osc = O.Scene(cp1, c1.types, c1.leaf_depth)
+    o = osc.intersect(c1.primary)
+    assert_gate(gate(g, o, c1.primary, osc, c1.diameter, c1.leaf_depth, label="torus512-refit"))
+    gsc.refit(torch.from_numpy(c1.cp))  # host input
+    back = run(gsc, c1.primary)
+    assert np.array_equal(back.view(np.uint32), base.view(np.uint32))
+
+
+def test_instanced_1m_full_size_sampled(ccs):
+    """1,000,000 patches, 1920x1080 primary + secondary rays in the launch the
+    benchmark times; the oracle checks a seeded sample of each class."""
+    _say("generating the 1M-patch scene")
+    w = S.config2()
+    gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
+    osc = O.Scene(w.cp, w.types, w.leaf_depth)
+    for cls, rays in (("primary", w.primary), ("diffuse", w.diffuse)):
+        _say(f"1M {cls}: {len(rays)} rays on the GPU")
+        g = run(gsc, rays)
+        sel = S.sample_indices(len(rays), 4096, seed=77 if cls == "primary" else 78)
+        o = osc.intersect(rays[sel])
+        rep = gate(g[sel], o, rays[sel], osc, w.diameter, w.leaf_depth, label=f"1M-{cls}-sample")
+        assert_gate(rep, min_match=0.999)
+        assert rep["oracle_hits"] > 500

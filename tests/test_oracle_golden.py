@@ -23,4 +23,4 @@ def test_oracle_matches_stored_fixture(c1, c1_oracle):
         np.testing.assert_array_equal(h["id"], np.array([int(r[3]) for r in sub], np.uint32))
         np.testing.assert_array_equal(h["u"], np.array([float(r[4]) for r in sub]))
         np.testing.assert_array_equal(h["v"], np.array([float(r[5]) for r in sub]))
-        np.testing.assert_array_equal(h["counters"], np.array([[int(x) for x in r[6:12]] for r in sub]))
+        np.testing.assert_array_equal(h["counters"], np.array([[int(x) for x in r[6:14]] for r in sub]))
