@@ -28,15 +28,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MRays/s primary+diffuse at 1M patches: plain vs learned-order batched, oracle-exact"
 
-# Algorithmic 32-bit VALU operations per counted unit of work (fp32 add, mul,
-# fma, 2- or 3-operand min/max, compare, select, bit op: 1 each; a de Casteljau
-# midpoint (a+b)/2: 2; a division: 1).  Derived from the method's arithmetic,
-# not from the compiled code; the derivation is in the design doc.
+# Algorithmic 32-bit VALU operations per counted unit of work: the fewest gfx950
+# vector operations the arithmetic needs (add, sub, mul, fma, 2- or 3-operand
+# min/max, compare, select, bit op, and the midpoint (a+b)/2 as one add with the
+# /2 output modifier: 1 each; a division: 1).  Derived from the method's
+# arithmetic, not from the compiled code; the derivation is in the design doc.
 OPS_PER_UNIT = {
     "ray": 25,         # ray setup (validity, reciprocals) and the hit write
-    "node": 44,        # BVH node: two slab tests, ordering, stack push
-    "cand": 12,        # candidate patch: anchored origin and its products
-    "split": 334,      # Alg. 3 step: split 4x4x3 at 1/2, two boxes, two slab tests, choice, path bits
+    "node": 58,        # BVH node: two slab tests (25 each), ordering, stack push
+    "cand": 12,        # candidate patch: anchored origin
+    "split": 276,      # Alg. 3 step: 72 midpoints, two boxes (96), two slab tests (50), choice (22), 36 selects
     "backtrack": 6,    # count-trailing-zeros, path and trail update
     "greg": 622,       # Alg. 2 on a domain: extreme blends, displacement, crop of the lower grid
     "leaf": 30,        # leaf record: compare, (u, v) from the path code
@@ -91,6 +92,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-counters", action="store_true", help="skip the counted launch (roofline)")
+    ap.add_argument("--launch", default="", help="waves_per_cu,fetch_min,traverse_min,grid_min (default: library's)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,6 +116,9 @@ def main():
     scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
     torch.cuda.synchronize()
     create_s = time.time() - t0
+    if args.launch:
+        scene.set_launch(*[int(x) for x in args.launch.split(",")])
+    launch = scene.get_launch()
     info = scene.info()
     log(f"scene: {info['n_nodes']} nodes, BVH depth {info['bvh_depth']}, {info['device_bytes'] / 2**20:.1f} MiB, "
         f"create {create_s:.2f} s (host BVH {info['build_seconds']:.2f} s)")
@@ -174,7 +179,7 @@ def main():
         bytes_launch = traffic_from_profiles(launch_ms)
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
                     "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                    "traffic": bytes_launch, "kernel": "k_intersect<false>",
+                    "traffic": bytes_launch, "kernel": "k_trace<false>",
                     "kernel_avg_ms": round(launch_ms, 4),
                     "ops_per_launch": (ops_p + ops_d) / 2.0,
                     "ops_per_ray": {"primary": ops_p / n_p, "diffuse": ops_d / n_d}}
@@ -228,6 +233,7 @@ def main():
         "config": {"workload": (f"{w.name}: {w.cp.shape[0]} patches "
                                 f"({int(w.types.sum())} Gregory), {n_p} primary + {n_d} secondary rays per step"),
                    "variant": "plain (closest-first order, one launch per ray class)",
+                   "launch": launch,
                    "leaf_depth": w.leaf_depth},
         "per_class": per_class,
         "roofline": roofline,

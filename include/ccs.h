@@ -123,7 +123,9 @@ ccs_status ccs_refit(ccs_scene* scene, const float* control_points, int32_t loca
  * nearest first, the best distance so far pruning both).  rays and hits are
  * device pointers owned by the caller; n == 0 is a no-op.  Asynchronous on
  * `stream`.  Deterministic: the result of each ray does not depend on launch
- * geometry or on the other rays. */
+ * geometry or on the other rays.  Each call takes one of 256 per-scene
+ * ray-queue counters in turn: at most 256 calls on one scene may be in flight
+ * at once (across all streams). */
 ccs_status ccs_intersect(const ccs_scene* scene, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
                          void* stream);
 
@@ -135,6 +137,28 @@ ccs_status ccs_intersect(const ccs_scene* scene, const ccs_ray* rays, uint32_t n
  * same kernel; used for measurement. */
 ccs_status ccs_intersect_counted(const ccs_scene* scene, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
                                  uint32_t* counters, void* stream);
+
+/* Launch configuration of the intersection kernel.  Results never depend on
+ * it (each ray's computation is independent of which lane runs it and when);
+ * only the speed does.  The kernel keeps persistent waves whose lanes each
+ * carry a ray through fetch, traversal, subdivision steps and grid
+ * recomputations; a wave runs the fetch, traversal or recompute phase only when
+ * at least the given number of its 64 lanes waits for it (or nothing else can
+ * run), so that these divergent phases run on filled waves. */
+typedef struct ccs_launch_params {
+  uint32_t waves_per_cu;   /* resident waves per compute unit; 0 = as many as fit */
+  uint32_t fetch_min;      /* 1..64 lanes waiting for a new ray */
+  uint32_t traverse_min;   /* 1..64 lanes waiting to traverse to their next candidate */
+  uint32_t grid_min;       /* 1..64 lanes waiting for a grid recomputation */
+} ccs_launch_params;
+
+/* Sets the launch configuration used by later ccs_intersect* calls on the
+ * scene.  Defaults: {0, 16, 16, 16}.  CCS_ERR_INVALID_ARG for thresholds
+ * outside [1, 64].  Not synchronized with calls in flight on other threads. */
+ccs_status ccs_scene_set_launch(ccs_scene* scene, const ccs_launch_params* params);
+
+/* The current launch configuration, waves_per_cu resolved to the number used. */
+ccs_status ccs_scene_get_launch(const ccs_scene* scene, ccs_launch_params* params);
 
 /* Secondary rays from hits (Sec. 3.3, self-intersection): for hit i the origin is
  * o + t d moved along the unit normal f_u x f_v at (u, v) (turned against d) by

@@ -3,13 +3,16 @@
 A ray matches when both miss, or both hit the same patch with |dt| <= 1e-4 D
 (D = scene diagonal) and |du|, |dv| <= 2^-L.  Otherwise it is a disagreement,
 excused only when the paper's error model explains it:
-  * tie   -- the GPU's leaf is, by the oracle's own FP64 arithmetic, entered
-             within 1e-4 D of the oracle's best distance (several leaves or
-             patches are then correct answers; Sec. 3.3 records the closest box);
-  * seam  -- the two hit points are within 1e-4 D of each other, or a reported
-             (u, v) lies within 2^-L of its patch boundary (shared edges);
-  * graze -- the ray only clips the leaf box the other side reported: its path
-             inside that box is shorter than 1e-4 D (silhouettes).
+  * tie   -- the GPU's leaf is, by the oracle's own FP64 arithmetic, hit and
+             entered within 1e-5 max(t, 1) of the oracle's best distance (its
+             own t within the 1e-4 D tolerance): two leaves or patches are then
+             equally correct answers (Sec. 3.3 records the closest box);
+  * seam  -- different patches: the two hit points are within 1e-4 D of each
+             other, or a reported (u, v) lies within 2^-L of its patch boundary
+             (shared edges); a different leaf of the same patch is never a seam;
+  * graze -- the ray only clips the leaf box the side that hit reported: its path
+             inside that box is shorter than 1e-3 of the box diagonal (plus
+             1e-6 (t + 1) of rounding): silhouettes, box edges and corners.
 The gate: identical hit/miss and patch id on >= 99.99 % of the rays of a class,
 and every disagreement (in hit/miss, patch, t, u or v) excused.
 """
@@ -36,7 +39,7 @@ def _path_in_box(ray, lo, hi):
             continue
         t0, t1 = (lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]
         near, far = max(near, min(t0, t1)), min(far, max(t0, t1))
-    return (far - near) * np.linalg.norm(d)
+    return (far - near) * np.linalg.norm(d)  # negative when the box is missed
 
 
 def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: float, leaf_depth: int,
@@ -51,7 +54,9 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
     gt = gpu[:, 0].astype(np.float64)
     both_miss = ~g_hit & ~o_hit
     same = g_hit & o_hit & (gid == oid)
-    close = same & (np.abs(gt - ora["t"]) <= tol_t) & (np.abs(gpu[:, 2] - ora["u"]) <= tol_uv) & \
+    with np.errstate(invalid="ignore"):  # inf - inf on rays both sides miss
+        dt_ok = np.abs(gt - ora["t"]) <= tol_t
+    close = same & dt_ok & (np.abs(gpu[:, 2] - ora["u"]) <= tol_uv) & \
         (np.abs(gpu[:, 3] - ora["v"]) <= tol_uv)
     match = both_miss | close
     kinds = {"tie": 0, "seam": 0, "graze": 0, "hard": 0}
@@ -59,12 +64,12 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
     for k in np.where(~match)[0]:
         ray = rays[k]
         kind = "hard"
-        if g_hit[k]:
+        if g_hit[k] and o_hit[k]:
             e = osc.leaf_entry(gid[k], ray, gpu[k, 2], gpu[k, 3])
-            best_o = ora["t"][k] if o_hit[k] else np.inf
-            if np.isfinite(e) and abs(e - gt[k]) <= tol_t and e <= best_o + tol_t:
+            tol_tie = 1e-5 * max(ora["t"][k], 1.0)
+            if np.isfinite(e) and abs(e - gt[k]) <= tol_t and e <= ora["t"][k] + tol_tie:
                 kind = "tie"
-        if kind == "hard" and g_hit[k] and o_hit[k]:
+        if kind == "hard" and g_hit[k] and o_hit[k] and gid[k] != oid[k]:
             o64, d64 = ray[:3].astype(np.float64), ray[4:7].astype(np.float64)
             xg, xo = o64 + gt[k] * d64, o64 + ora["t"][k] * d64
             m = 2.0 ** -leaf_depth
@@ -74,11 +79,12 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
                 kind = "seam"
         if kind == "hard":
             # the side that hit: does the ray merely clip its leaf box?
-            for side_hit, pid, u, v in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k]),
-                                        (g_hit[k], gid[k], gpu[k, 2], gpu[k, 3])):
+            for side_hit, pid, u, v, t in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k], ora["t"][k]),
+                                           (g_hit[k], gid[k], gpu[k, 2], gpu[k, 3], gt[k])):
                 if side_hit:
                     lo, hi = osc.leaf_box(pid, u, v)
-                    if _path_in_box(ray, lo, hi) <= tol_t:
+                    slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-6 * (abs(t) + 1.0)
+                    if abs(_path_in_box(ray, lo, hi)) <= slack:
                         kind = "graze"
                         break
         kinds[kind] += 1

@@ -22,7 +22,8 @@ NO_HIT = 0xFFFFFFFF
 COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
 
 EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_counted", "ccs_bounce",
-           "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error")
+           "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
+           "ccs_scene_get_launch")
 
 
 class CcsError(RuntimeError):
@@ -41,6 +42,11 @@ class SceneInfo(C.Structure):
     _fields_ = [("n_patches", C.c_uint32), ("n_nodes", C.c_uint32), ("leaf_depth", C.c_uint32),
                 ("bvh_depth", C.c_uint32), ("device_bytes", C.c_uint64), ("lo", C.c_float * 3),
                 ("hi", C.c_float * 3), ("build_seconds", C.c_double)]
+
+
+class LaunchParams(C.Structure):
+    _fields_ = [("waves_per_cu", C.c_uint32), ("fetch_min", C.c_uint32), ("traverse_min", C.c_uint32),
+                ("grid_min", C.c_uint32)]
 
 
 _lib = None
@@ -64,6 +70,8 @@ def lib():
         L.ccs_scene_destroy.argtypes = [vp]
         L.ccs_scene_destroy.restype = None
         L.ccs_last_error.restype = C.c_char_p
+        L.ccs_scene_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
+        L.ccs_scene_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         for name in EXPORTS:
             if name not in ("ccs_scene_destroy", "ccs_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -133,6 +141,16 @@ class Scene:
         return dict(n_patches=i.n_patches, n_nodes=i.n_nodes, leaf_depth=i.leaf_depth, bvh_depth=i.bvh_depth,
                     device_bytes=int(i.device_bytes), lo=list(i.lo), hi=list(i.hi),
                     build_seconds=i.build_seconds)
+
+    def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 16, grid_min: int = 16):
+        p = LaunchParams(waves_per_cu, fetch_min, traverse_min, grid_min)
+        _check(lib().ccs_scene_set_launch(self._h, C.byref(p)))
+
+    def get_launch(self) -> dict:
+        p = LaunchParams()
+        _check(lib().ccs_scene_get_launch(self._h, C.byref(p)))
+        return dict(waves_per_cu=p.waves_per_cu, fetch_min=p.fetch_min, traverse_min=p.traverse_min,
+                    grid_min=p.grid_min)
 
     @staticmethod
     def _rays(rays):

@@ -2,6 +2,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -28,6 +29,7 @@ ccs_status hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr int kTraversalStack = 48;  // matches the LDS stack of the intersect kernel
+constexpr uint32_t kQueueSlots = 256;  // ray-queue counters, one per launch in flight on a scene
 
 }  // namespace
 
@@ -39,6 +41,9 @@ struct ccs_scene {
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   double build_seconds = 0.0;
   float* cp_stage = nullptr;  // device staging buffer for host refit input
+  uint32_t* queues = nullptr;  // kQueueSlots ray-queue counters
+  std::atomic<uint32_t> next_queue{0};
+  ccs_launch_params launch{0, 16, 16, 16};
   std::vector<void*> allocations;
 };
 
@@ -205,7 +210,7 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
   if ((st = dev_alloc(s, &nodes, (size_t)n_nodes * 4)) != CCS_OK || (st = dev_alloc(s, &drec, recs.size())) != CCS_OK ||
       (st = dev_alloc(s, &perm, n)) != CCS_OK || (st = dev_alloc(s, &invp, n)) != CCS_OK ||
       (st = dev_alloc(s, &lpar, n)) != CCS_OK || (st = dev_alloc(s, &npar, n_nodes)) != CCS_OK ||
-      (st = dev_alloc(s, &arr, n_nodes)) != CCS_OK) {
+      (st = dev_alloc(s, &arr, n_nodes)) != CCS_OK || (st = dev_alloc(s, &s->queues, kQueueSlots)) != CCS_OK) {
     free_scene(s);
     return st;
   }
@@ -240,6 +245,13 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
   D.leaf_parent = lpar;
   D.node_parent = npar;
   D.arrivals = arr;
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    free_scene(s);
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  D.n_cus = (uint32_t)std::max(1, cus);
   *out = s;
   return CCS_OK;
 }
@@ -271,14 +283,23 @@ ccs_status ccs_refit(ccs_scene* s, const float* control_points, int32_t location
   return CCS_OK;
 }
 
+static ccs_status intersect_impl(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
+                                 uint32_t* counters, void* stream) {
+  ccs_scene* m = const_cast<ccs_scene*>(s);
+  const uint32_t slot = m->next_queue.fetch_add(1) % kQueueSlots;
+  ccs::LaunchParams lp{s->launch.fetch_min, s->launch.traverse_min, s->launch.grid_min, s->queues + slot};
+  hipError_t e = ccs::launch_intersect(s->dev, rays, n, hits, counters, lp, s->launch.waves_per_cu,
+                                       (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "intersect launch");
+  return CCS_OK;
+}
+
 ccs_status ccs_intersect(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, void* stream) {
   g_error.clear();
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n == 0) return CCS_OK;
   if (!rays || !hits) return fail(CCS_ERR_INVALID_ARG, "rays or hits is NULL");
-  hipError_t e = ccs::launch_intersect(s->dev, rays, n, hits, nullptr, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "intersect launch");
-  return CCS_OK;
+  return intersect_impl(s, rays, n, hits, nullptr, stream);
 }
 
 ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
@@ -287,8 +308,24 @@ ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n == 0) return CCS_OK;
   if (!rays || !hits || !counters) return fail(CCS_ERR_INVALID_ARG, "rays, hits or counters is NULL");
-  hipError_t e = ccs::launch_intersect(s->dev, rays, n, hits, counters, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "intersect launch");
+  return intersect_impl(s, rays, n, hits, counters, stream);
+}
+
+ccs_status ccs_scene_set_launch(ccs_scene* s, const ccs_launch_params* p) {
+  g_error.clear();
+  if (!s || !p) return fail(CCS_ERR_INVALID_ARG, "scene or params is NULL");
+  if (p->fetch_min < 1 || p->fetch_min > 64 || p->traverse_min < 1 || p->traverse_min > 64 || p->grid_min < 1 ||
+      p->grid_min > 64)
+    return fail(CCS_ERR_INVALID_ARG, "phase thresholds must be in [1, 64]");
+  s->launch = *p;
+  return CCS_OK;
+}
+
+ccs_status ccs_scene_get_launch(const ccs_scene* s, ccs_launch_params* p) {
+  g_error.clear();
+  if (!s || !p) return fail(CCS_ERR_INVALID_ARG, "scene or params is NULL");
+  *p = s->launch;
+  if (p->waves_per_cu == 0) p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false);
   return CCS_OK;
 }
 

@@ -25,10 +25,19 @@ struct DeviceScene {
   const int32_t* leaf_parent;  // record -> (node << 1 | side)
   const int32_t* node_parent;  // node -> (parent << 1 | side), -1 for the root
   uint32_t* arrivals;        // n_nodes counters for the bottom-up refit
+  uint32_t n_cus;            // compute units of the device
 };
 
+// Phase thresholds of the persistent intersection kernel (see trace.hip) and
+// the launch's ray-queue counter.
+struct LaunchParams {
+  uint32_t fetch_min, traverse_min, grid_min;
+  uint32_t* queue;
+};
+
+int max_waves_per_cu(bool counted);
 hipError_t launch_intersect(const DeviceScene& s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, uint32_t* counters,
-                            hipStream_t stream);
+                            const LaunchParams& lp, uint32_t waves_per_cu, hipStream_t stream);
 hipError_t launch_refit(const DeviceScene& s, const float* cp_world, hipStream_t stream);
 hipError_t launch_bounce(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                          uint32_t n, ccs_ray* out, hipStream_t stream);

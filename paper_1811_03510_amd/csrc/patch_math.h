@@ -97,25 +97,27 @@ __device__ __forceinline__ void take_half(const Split1& s, bool second, float g[
 }
 
 // ---------------------------------------------------------------- ray / box
-struct RayP {  // ray in a patch's anchored frame
-  float ox, oy, oz;   // origin - anchor
-  float ix, iy, iz;   // 1/d (zero components replaced by +-1e30)
-  float cx, cy, cz;   // -o * (1/d)
+struct RayP {  // a ray in some frame: origin, reciprocal direction, tmin
+  float ox, oy, oz;
+  float ix, iy, iz;  // 1/d (zero components replaced by +-1e30)
   float tmin;
 };
 
 // 1 + 2*gamma_3 with gamma_n = n u / (1 - n u), u = 2^-24: widening the far
 // distance by it makes the fp32 slab test conservative against the rounding
 // of the plane distances (robust BVH traversal of Ize 2013, cited in Sec. 3.4).
+// The distances are formed as (plane - o) * (1/d): two roundings, each relative
+// to the distance itself, which is what the widening covers (a precomputed
+// -o/d would carry an error relative to |o|/|d|, not to the distance).
 constexpr float kFarScale = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);
 
 // Closed slab test on [tmin, cap]; returns the entry distance or +inf when missed.
 __device__ __forceinline__ float slab(const RayP& r, float lx, float ly, float lz, float hx, float hy, float hz,
                                       float cap) {
-  float tx0 = fmaf(lx, r.ix, r.cx), tx1 = fmaf(hx, r.ix, r.cx);
-  float ty0 = fmaf(ly, r.iy, r.cy), ty1 = fmaf(hy, r.iy, r.cy);
-  float tz0 = fmaf(lz, r.iz, r.cz), tz1 = fmaf(hz, r.iz, r.cz);
-  float nr = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
+  const float tx0 = (lx - r.ox) * r.ix, tx1 = (hx - r.ox) * r.ix;
+  const float ty0 = (ly - r.oy) * r.iy, ty1 = (hy - r.oy) * r.iy;
+  const float tz0 = (lz - r.oz) * r.iz, tz1 = (hz - r.oz) * r.iz;
+  const float nr = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
   float fr = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * kFarScale;
   fr = fminf(fr, cap);
   return nr <= fr ? nr : __builtin_inff();
@@ -240,7 +242,8 @@ __device__ __forceinline__ void calc_points_and_d(const PatchPts& P, bool gregor
       const int i = (k & 1) ? 2 : 1, j = (k & 2) ? 2 : 1;
       const float dul = (i == 1) ? u0 : 1.0f - u1, duh = (i == 1) ? u1 : 1.0f - u0;
       const float dvl = (j == 1) ? v0 : 1.0f - v1, dvh = (j == 1) ? v1 : 1.0f - v0;
-      const float lam_lo = __fdiv_rn(dul, dul + dvh), lam_hi = __fdiv_rn(duh, duh + dvl);
+      // hardware reciprocal (1 ulp): moves A, B by a rounding-sized amount, like the crop itself
+      const float lam_lo = dul * __builtin_amdgcn_rcpf(dul + dvh), lam_hi = duh * __builtin_amdgcn_rcpf(duh + dvl);
       const float w = ((i == 1) ? wu1 : wu2) * ((j == 1) ? wv1 : wv2);
       const float px = P.x[i][j], py = P.y[i][j], pz = P.z[i][j];
       const float ex = px - P.vx[k], ey = py - P.vy[k], ez = pz - P.vz[k];

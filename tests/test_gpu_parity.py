@@ -59,6 +59,20 @@ def test_ragged_launches_are_bitwise_identical(ccs, c1, c1_gpu):
         assert np.array_equal(part.view(np.uint32), full[idx].view(np.uint32)), n
 
 
+def test_launch_configuration_never_changes_results(ccs, c1, c1_gpu):
+    """Persistent waves, phase thresholds and waves per CU only change speed."""
+    rays = np.concatenate([c1.primary, c1.diffuse])
+    c1_gpu.set_launch()
+    base = run(c1_gpu, rays)
+    for w, f, t, g in ((1, 1, 1, 1), (0, 64, 64, 64), (2, 8, 32, 4), (0, 1, 64, 1), (3, 33, 2, 64)):
+        _say(f"launch waves/CU={w} fetch>={f} traverse>={t} grid>={g}")
+        c1_gpu.set_launch(w, f, t, g)
+        assert np.array_equal(run(c1_gpu, rays).view(np.uint32), base.view(np.uint32)), (w, f, t, g)
+    c1_gpu.set_launch()
+    with pytest.raises(ccs.CcsError):
+        c1_gpu.set_launch(0, 0, 16, 16)
+
+
 def test_counted_kernel_gives_the_same_hits(ccs, c1, c1_gpu, c1_oracle):
     r = torch.from_numpy(c1.primary).cuda()
     h0 = c1_gpu.intersect(r)
