@@ -95,6 +95,7 @@ typedef struct ccs_scene_info {
   uint64_t device_bytes;  /* device memory owned by the scene */
   float lo[3], hi[3];     /* scene bounds (union of patch boxes) */
   double build_seconds;   /* host BVH build time */
+  uint32_t n_frames;      /* geometry frames held (animation playback) */
 } ccs_scene_info;
 
 /* Builds a scene (Sec. 3: patch bounds, then a hierarchy over them).
@@ -118,6 +119,35 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out);
  * Host input is scanned for non-finite values (CCS_ERR_INVALID_ARG); device input
  * is not scanned (non-finite points then give unspecified hits, never a fault). */
 ccs_status ccs_refit(ccs_scene* scene, const float* control_points, int32_t location, void* stream);
+
+/* Frames (animation playback, the use case named in the abstract): a scene can
+ * hold n_frames copies of its patch geometry that share one BVH topology.
+ * Frame 0 is the creation geometry; ccs_scene_set_frames copies it into every
+ * frame, after which ccs_refit_frame moves one frame's control points.
+ * Synchronizes the device; frees and re-allocates the frame storage
+ * (n_frames x (256 B per patch + 64 B per node)).  1 <= n_frames <= 4096. */
+ccs_status ccs_scene_set_frames(ccs_scene* scene, uint32_t n_frames);
+
+/* ccs_refit applied to one frame (ccs_refit is frame 0). */
+ccs_status ccs_refit_frame(ccs_scene* scene, uint32_t frame, const float* control_points, int32_t location,
+                           void* stream);
+
+/* One batch of a batched launch: n rays traced against `frame`. */
+typedef struct ccs_batch {
+  uint32_t frame;
+  uint32_t n;
+  const ccs_ray* rays;  /* device, n rays */
+  ccs_hit* hits;        /* device, n hits */
+} ccs_batch;
+
+/* Closest hits of several batches of uneven size, possibly of different
+ * frames, in one persistent launch with one ray queue over all of them (no
+ * per-batch tail).  batches is a host array of at most 32 entries, copied into
+ * the launch's arguments: it may be freed on return, and the launch can be
+ * captured in a HIP graph.  Each hit equals what ccs_intersect gives for that
+ * ray on that frame.  Asynchronous on `stream`; at most 2^31 - 1 rays. */
+ccs_status ccs_intersect_batched(const ccs_scene* scene, const ccs_batch* batches, uint32_t n_batches,
+                                 void* stream);
 
 /* Closest hits of n rays (Alg. 3 per candidate patch, candidates from the BVH
  * nearest first, the best distance so far pruning both).  rays and hits are
@@ -150,10 +180,11 @@ typedef struct ccs_launch_params {
   uint32_t fetch_min;      /* 1..64 lanes waiting for a new ray */
   uint32_t traverse_min;   /* 1..64 lanes waiting to traverse to their next candidate */
   uint32_t grid_min;       /* 1..64 lanes waiting for a grid recomputation */
+  uint32_t traverse_steps; /* BVH nodes a lane visits per traversal phase; 0 = until it reaches a candidate */
 } ccs_launch_params;
 
 /* Sets the launch configuration used by later ccs_intersect* calls on the
- * scene.  Defaults: {0, 16, 16, 16}.  CCS_ERR_INVALID_ARG for thresholds
+ * scene.  Defaults: {0, 16, 1, 16, 2}.  CCS_ERR_INVALID_ARG for thresholds
  * outside [1, 64].  Not synchronized with calls in flight on other threads. */
 ccs_status ccs_scene_set_launch(ccs_scene* scene, const ccs_launch_params* params);
 

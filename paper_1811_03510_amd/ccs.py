@@ -23,7 +23,8 @@ COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "
 
 EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_counted", "ccs_bounce",
            "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
-           "ccs_scene_get_launch")
+           "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched")
+MAX_BATCHES = 32
 
 
 class CcsError(RuntimeError):
@@ -41,12 +42,16 @@ class SceneDesc(C.Structure):
 class SceneInfo(C.Structure):
     _fields_ = [("n_patches", C.c_uint32), ("n_nodes", C.c_uint32), ("leaf_depth", C.c_uint32),
                 ("bvh_depth", C.c_uint32), ("device_bytes", C.c_uint64), ("lo", C.c_float * 3),
-                ("hi", C.c_float * 3), ("build_seconds", C.c_double)]
+                ("hi", C.c_float * 3), ("build_seconds", C.c_double), ("n_frames", C.c_uint32)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("frame", C.c_uint32), ("n", C.c_uint32), ("rays", C.c_void_p), ("hits", C.c_void_p)]
 
 
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_cu", C.c_uint32), ("fetch_min", C.c_uint32), ("traverse_min", C.c_uint32),
-                ("grid_min", C.c_uint32)]
+                ("grid_min", C.c_uint32), ("traverse_steps", C.c_uint32)]
 
 
 _lib = None
@@ -71,6 +76,9 @@ def lib():
         L.ccs_scene_destroy.restype = None
         L.ccs_last_error.restype = C.c_char_p
         L.ccs_scene_set_launch.argtypes = [vp, C.POINTER(LaunchParams)]
+        L.ccs_scene_set_frames.argtypes = [vp, u32]
+        L.ccs_refit_frame.argtypes = [vp, u32, vp, i32, vp]
+        L.ccs_intersect_batched.argtypes = [vp, C.POINTER(Batch), u32, vp]
         L.ccs_scene_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         for name in EXPORTS:
             if name not in ("ccs_scene_destroy", "ccs_last_error"):
@@ -140,17 +148,47 @@ class Scene:
         _check(lib().ccs_scene_info_get(self._h, C.byref(i)))
         return dict(n_patches=i.n_patches, n_nodes=i.n_nodes, leaf_depth=i.leaf_depth, bvh_depth=i.bvh_depth,
                     device_bytes=int(i.device_bytes), lo=list(i.lo), hi=list(i.hi),
-                    build_seconds=i.build_seconds)
+                    build_seconds=i.build_seconds, n_frames=i.n_frames)
 
-    def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 16, grid_min: int = 16):
-        p = LaunchParams(waves_per_cu, fetch_min, traverse_min, grid_min)
+    def set_frames(self, n_frames: int):
+        _check(lib().ccs_scene_set_frames(self._h, int(n_frames)))
+
+    def refit_frame(self, frame: int, control_points, stream=None):
+        import torch
+        cp = torch.as_tensor(control_points)
+        if cp.dtype != torch.float32 or cp.numel() != self.n * 60:
+            raise ValueError("refit input must be float32 with n x 20 x 3 values")
+        cp = cp.contiguous()
+        keep = getattr(self, "_refit_keep_frames", {})
+        keep[int(frame)] = cp  # device input must outlive the queued work
+        self._refit_keep_frames = keep
+        _check(lib().ccs_refit_frame(self._h, int(frame), _ptr(cp), CCS_DEVICE if cp.is_cuda else CCS_HOST,
+                                     _stream(stream)))
+
+    def intersect_batched(self, batches, stream=None):
+        """batches: list of (frame, rays (N, 8) cuda float32, hits (N, 4) cuda float32 or None).
+        Returns the list of hit tensors (one launch for all batches)."""
+        import torch
+        out, arr = [], (Batch * max(1, len(batches)))()
+        for k, (frame, rays, hits) in enumerate(batches):
+            r = self._rays(rays)
+            if hits is None:
+                hits = torch.empty((r.shape[0], 4), dtype=torch.float32, device=r.device)
+            arr[k] = Batch(int(frame), r.shape[0], r.data_ptr(), hits.data_ptr())
+            out.append(hits)
+        _check(lib().ccs_intersect_batched(self._h, arr, len(batches), _stream(stream)))
+        return out
+
+    def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 1, grid_min: int = 16,
+                   traverse_steps: int = 2):
+        p = LaunchParams(waves_per_cu, fetch_min, traverse_min, grid_min, traverse_steps)
         _check(lib().ccs_scene_set_launch(self._h, C.byref(p)))
 
     def get_launch(self) -> dict:
         p = LaunchParams()
         _check(lib().ccs_scene_get_launch(self._h, C.byref(p)))
         return dict(waves_per_cu=p.waves_per_cu, fetch_min=p.fetch_min, traverse_min=p.traverse_min,
-                    grid_min=p.grid_min)
+                    grid_min=p.grid_min, traverse_steps=p.traverse_steps)
 
     @staticmethod
     def _rays(rays):
@@ -179,7 +217,7 @@ class Scene:
         _check(lib().ccs_intersect_counted(self._h, _ptr(r), n, _ptr(hits), _ptr(cnt), _stream(stream)))
         return hits, cnt
 
-    def refit(self, control_points, stream=None):
+    def refit(self, control_points, stream=None):  # frame 0
         import torch
         cp = torch.as_tensor(control_points)
         if cp.dtype != torch.float32 or cp.numel() != self.n * 60:

@@ -43,7 +43,7 @@ struct ccs_scene {
   float* cp_stage = nullptr;  // device staging buffer for host refit input
   uint32_t* queues = nullptr;  // kQueueSlots ray-queue counters
   std::atomic<uint32_t> next_queue{0};
-  ccs_launch_params launch{0, 16, 16, 16};
+  ccs_launch_params launch{0, 16, 1, 16, 2};
   std::vector<void*> allocations;
 };
 
@@ -63,6 +63,16 @@ ccs_status dev_alloc(ccs_scene* s, T** p, size_t count) {
   s->device_bytes += count * sizeof(T);
   *p = static_cast<T*>(q);
   return CCS_OK;
+}
+
+void dev_free(ccs_scene* s, void* p, size_t bytes) {
+  for (size_t k = 0; k < s->allocations.size(); ++k)
+    if (s->allocations[k] == p) {
+      (void)hipFree(p);
+      s->allocations.erase(s->allocations.begin() + (long)k);
+      s->device_bytes -= bytes;
+      return;
+    }
 }
 
 void free_scene(ccs_scene* s) {
@@ -252,13 +262,55 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
     return hip_fail(e, "hipDeviceGetAttribute");
   }
   D.n_cus = (uint32_t)std::max(1, cus);
+  D.n_frames = 1;
+  D.frame_rec_floats = (size_t)n * ccs::kRecFloats;
+  D.frame_node_f4 = (size_t)n_nodes * 4;
   *out = s;
   return CCS_OK;
 }
 
-ccs_status ccs_refit(ccs_scene* s, const float* control_points, int32_t location, void* stream) {
+ccs_status ccs_scene_set_frames(ccs_scene* s, uint32_t n_frames) {
   g_error.clear();
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (n_frames < 1 || n_frames > 4096) return fail(CCS_ERR_INVALID_ARG, "n_frames must be in [1, 4096]");
+  ccs::DeviceScene& D = s->dev;
+  if (n_frames == D.n_frames) return CCS_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronizing before re-allocating frames");
+  float* recs = nullptr;
+  float4* nodes = nullptr;
+  ccs_status st = dev_alloc(s, &recs, D.frame_rec_floats * n_frames);
+  if (st != CCS_OK) return st;
+  st = dev_alloc(s, &nodes, D.frame_node_f4 * n_frames);
+  if (st != CCS_OK) {
+    dev_free(s, recs, D.frame_rec_floats * n_frames * sizeof(float));
+    return st;
+  }
+  // every frame starts as a copy of frame 0
+  for (uint32_t f = 0; f < n_frames && e == hipSuccess; ++f) {
+    if (D.frame_rec_floats)
+      e = hipMemcpy(recs + f * D.frame_rec_floats, D.recs, D.frame_rec_floats * sizeof(float), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess && D.frame_node_f4)
+      e = hipMemcpy(nodes + f * D.frame_node_f4, D.nodes, D.frame_node_f4 * sizeof(float4), hipMemcpyDeviceToDevice);
+  }
+  if (e != hipSuccess) {
+    dev_free(s, recs, D.frame_rec_floats * n_frames * sizeof(float));
+    dev_free(s, nodes, D.frame_node_f4 * n_frames * sizeof(float4));
+    return hip_fail(e, "copying frame 0");
+  }
+  dev_free(s, D.recs, D.frame_rec_floats * D.n_frames * sizeof(float));
+  dev_free(s, const_cast<float4*>(D.nodes), D.frame_node_f4 * D.n_frames * sizeof(float4));
+  D.recs = recs;
+  D.nodes = nodes;
+  D.n_frames = n_frames;
+  return CCS_OK;
+}
+
+ccs_status ccs_refit_frame(ccs_scene* s, uint32_t frame, const float* control_points, int32_t location,
+                           void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (frame >= s->dev.n_frames) return fail(CCS_ERR_INVALID_ARG, "frame out of range");
   if (s->dev.n_patches == 0) return CCS_OK;
   if (!control_points) return fail(CCS_ERR_INVALID_ARG, "control_points is NULL");
   if (location != CCS_HOST && location != CCS_DEVICE)
@@ -278,20 +330,37 @@ ccs_status ccs_refit(ccs_scene* s, const float* control_points, int32_t location
     if (e != hipSuccess) return hip_fail(e, "copying refit input");
     src = s->cp_stage;
   }
-  hipError_t e = ccs::launch_refit(s->dev, src, st);
+  ccs::DeviceScene f = s->dev;
+  f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
+  f.nodes = s->dev.nodes + frame * s->dev.frame_node_f4;
+  hipError_t e = ccs::launch_refit(f, src, st);
   if (e != hipSuccess) return hip_fail(e, "refit launch");
   return CCS_OK;
 }
 
-static ccs_status intersect_impl(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
-                                 uint32_t* counters, void* stream) {
+ccs_status ccs_refit(ccs_scene* s, const float* control_points, int32_t location, void* stream) {
+  return ccs_refit_frame(s, 0, control_points, location, stream);
+}
+
+static ccs_status launch_batches(const ccs_scene* s, const ccs::BatchTable& bt, uint32_t* counters, void* stream) {
   ccs_scene* m = const_cast<ccs_scene*>(s);
   const uint32_t slot = m->next_queue.fetch_add(1) % kQueueSlots;
-  ccs::LaunchParams lp{s->launch.fetch_min, s->launch.traverse_min, s->launch.grid_min, s->queues + slot};
-  hipError_t e = ccs::launch_intersect(s->dev, rays, n, hits, counters, lp, s->launch.waves_per_cu,
-                                       (hipStream_t)stream);
+  const uint32_t steps = s->launch.traverse_steps ? s->launch.traverse_steps : 0xFFFFFFFFu;
+  ccs::LaunchParams lp{s->launch.fetch_min, s->launch.traverse_min, s->launch.grid_min, steps, s->queues + slot};
+  hipError_t e = ccs::launch_intersect(s->dev, bt, counters, lp, s->launch.waves_per_cu, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "intersect launch");
   return CCS_OK;
+}
+
+static ccs::BatchTable one_batch(const ccs_ray* rays, uint32_t n, ccs_hit* hits) {
+  ccs::BatchTable bt{};
+  bt.n_batches = 1;
+  bt.prefix[0] = 0;
+  bt.prefix[1] = n;
+  bt.frame[0] = 0;
+  bt.rays[0] = rays;
+  bt.hits[0] = hits;
+  return bt;
 }
 
 ccs_status ccs_intersect(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, void* stream) {
@@ -299,7 +368,7 @@ ccs_status ccs_intersect(const ccs_scene* s, const ccs_ray* rays, uint32_t n, cc
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n == 0) return CCS_OK;
   if (!rays || !hits) return fail(CCS_ERR_INVALID_ARG, "rays or hits is NULL");
-  return intersect_impl(s, rays, n, hits, nullptr, stream);
+  return launch_batches(s, one_batch(rays, n, hits), nullptr, stream);
 }
 
 ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
@@ -308,7 +377,33 @@ ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n == 0) return CCS_OK;
   if (!rays || !hits || !counters) return fail(CCS_ERR_INVALID_ARG, "rays, hits or counters is NULL");
-  return intersect_impl(s, rays, n, hits, counters, stream);
+  return launch_batches(s, one_batch(rays, n, hits), counters, stream);
+}
+
+ccs_status ccs_intersect_batched(const ccs_scene* s, const ccs_batch* batches, uint32_t n_batches, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (n_batches == 0) return CCS_OK;
+  if (!batches) return fail(CCS_ERR_INVALID_ARG, "batches is NULL");
+  if (n_batches > (uint32_t)ccs::kMaxBatches)
+    return fail(CCS_ERR_INVALID_ARG, "at most " + std::to_string(ccs::kMaxBatches) + " batches per call");
+  ccs::BatchTable bt{};
+  uint64_t total = 0;
+  bt.n_batches = n_batches;
+  for (uint32_t b = 0; b < n_batches; ++b) {
+    const ccs_batch& x = batches[b];
+    if (x.frame >= s->dev.n_frames) return fail(CCS_ERR_INVALID_ARG, "batch frame out of range");
+    if (x.n > 0 && (!x.rays || !x.hits)) return fail(CCS_ERR_INVALID_ARG, "batch rays or hits is NULL");
+    bt.prefix[b] = (uint32_t)total;
+    bt.frame[b] = x.frame;
+    bt.rays[b] = x.rays;
+    bt.hits[b] = x.hits;
+    total += x.n;
+  }
+  if (total >= (1ull << 31)) return fail(CCS_ERR_INVALID_ARG, "more than 2^31 rays in one call");
+  bt.prefix[n_batches] = (uint32_t)total;
+  if (total == 0) return CCS_OK;
+  return launch_batches(s, bt, nullptr, stream);
 }
 
 ccs_status ccs_scene_set_launch(ccs_scene* s, const ccs_launch_params* p) {
@@ -354,6 +449,7 @@ ccs_status ccs_scene_info_get(const ccs_scene* s, ccs_scene_info* info) {
     info->hi[a] = s->hi[a];
   }
   info->build_seconds = s->build_seconds;
+  info->n_frames = s->dev.n_frames;
   return CCS_OK;
 }
 

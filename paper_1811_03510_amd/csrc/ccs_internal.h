@@ -26,18 +26,33 @@ struct DeviceScene {
   const int32_t* node_parent;  // node -> (parent << 1 | side), -1 for the root
   uint32_t* arrivals;        // n_nodes counters for the bottom-up refit
   uint32_t n_cus;            // compute units of the device
+  uint32_t n_frames;         // frames: copies of recs and node boxes sharing one topology
+  size_t frame_rec_floats;   // floats per frame in recs (n_patches * kRecFloats)
+  size_t frame_node_f4;      // float4s per frame in nodes (n_nodes * 4)
+};
+
+// Rays of one launch: up to kMaxBatches batches, each with its own frame, ray
+// array and hit array; ray k of the launch belongs to batch b when
+// prefix[b] <= k < prefix[b + 1].  Passed by value as a kernel argument.
+constexpr int kMaxBatches = 32;
+struct BatchTable {
+  uint32_t n_batches;
+  uint32_t prefix[kMaxBatches + 1];
+  uint32_t frame[kMaxBatches];
+  const ccs_ray* rays[kMaxBatches];
+  ccs_hit* hits[kMaxBatches];
 };
 
 // Phase thresholds of the persistent intersection kernel (see trace.hip) and
 // the launch's ray-queue counter.
 struct LaunchParams {
-  uint32_t fetch_min, traverse_min, grid_min;
+  uint32_t fetch_min, traverse_min, grid_min, traverse_steps;
   uint32_t* queue;
 };
 
 int max_waves_per_cu(bool counted);
-hipError_t launch_intersect(const DeviceScene& s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, uint32_t* counters,
-                            const LaunchParams& lp, uint32_t waves_per_cu, hipStream_t stream);
+hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
+                            uint32_t waves_per_cu, hipStream_t stream);
 hipError_t launch_refit(const DeviceScene& s, const float* cp_world, hipStream_t stream);
 hipError_t launch_bounce(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                          uint32_t n, ccs_ray* out, hipStream_t stream);

@@ -55,44 +55,46 @@ __device__ __forceinline__ Row7 casteljau_half(float a0, float a1, float a2, flo
   return r;
 }
 
-// One component of the split: E[b] = 7 points of row b; boxes of the register-
-// first half (points 0..3) and the register-second half (points 3..6).
-struct Split1 {
-  Row7 e[4];
-  float lo_a, hi_a, lo_b, hi_b;
+// Running slab test of the two child boxes, one component at a time, so that a
+// component's box bounds die as soon as they are folded in.  na/fa: entry and
+// exit of the register-first half so far, nb/fb: of the second half.
+struct SlabPair {
+  float na, fa, nb, fb;
 };
 
-__device__ __forceinline__ Split1 split_component(const float g[4][4]) {
-  Split1 s;
+// Splits component g, folds its child intervals [lo, hi + d] into s, and returns
+// the seven points of every row.
+__device__ __forceinline__ void split_fold(const float g[4][4], float o, float inv, float d, Row7 e[4], SlabPair& s) {
 #pragma unroll
-  for (int b = 0; b < 4; ++b) s.e[b] = casteljau_half(g[0][b], g[1][b], g[2][b], g[3][b]);
-  float la = min4(s.e[0].v[0], s.e[0].v[1], s.e[0].v[2], s.e[0].v[3]);
-  float ha = max4(s.e[0].v[0], s.e[0].v[1], s.e[0].v[2], s.e[0].v[3]);
-  float lb = min4(s.e[0].v[3], s.e[0].v[4], s.e[0].v[5], s.e[0].v[6]);
-  float hb = max4(s.e[0].v[3], s.e[0].v[4], s.e[0].v[5], s.e[0].v[6]);
+  for (int b = 0; b < 4; ++b) e[b] = casteljau_half(g[0][b], g[1][b], g[2][b], g[3][b]);
+  float la = min4(e[0].v[0], e[0].v[1], e[0].v[2], e[0].v[3]);
+  float ha = max4(e[0].v[0], e[0].v[1], e[0].v[2], e[0].v[3]);
+  float lb = min4(e[0].v[3], e[0].v[4], e[0].v[5], e[0].v[6]);
+  float hb = max4(e[0].v[3], e[0].v[4], e[0].v[5], e[0].v[6]);
 #pragma unroll
   for (int b = 1; b < 4; ++b) {
-    la = fminf(la, min4(s.e[b].v[0], s.e[b].v[1], s.e[b].v[2], s.e[b].v[3]));
-    ha = fmaxf(ha, max4(s.e[b].v[0], s.e[b].v[1], s.e[b].v[2], s.e[b].v[3]));
-    lb = fminf(lb, min4(s.e[b].v[3], s.e[b].v[4], s.e[b].v[5], s.e[b].v[6]));
-    hb = fmaxf(hb, max4(s.e[b].v[3], s.e[b].v[4], s.e[b].v[5], s.e[b].v[6]));
+    la = fminf(la, min4(e[b].v[0], e[b].v[1], e[b].v[2], e[b].v[3]));
+    ha = fmaxf(ha, max4(e[b].v[0], e[b].v[1], e[b].v[2], e[b].v[3]));
+    lb = fminf(lb, min4(e[b].v[3], e[b].v[4], e[b].v[5], e[b].v[6]));
+    hb = fmaxf(hb, max4(e[b].v[3], e[b].v[4], e[b].v[5], e[b].v[6]));
   }
-  s.lo_a = la;
-  s.hi_a = ha;
-  s.lo_b = lb;
-  s.hi_b = hb;
-  return s;
+  const float a0 = (la - o) * inv, a1 = (ha + d - o) * inv;
+  const float b0 = (lb - o) * inv, b1 = (hb + d - o) * inv;
+  s.na = fmaxf(s.na, fminf(a0, a1));
+  s.fa = fminf(s.fa, fmaxf(a0, a1));
+  s.nb = fmaxf(s.nb, fminf(b0, b1));
+  s.fb = fminf(s.fb, fmaxf(b0, b1));
 }
 
 // Chosen half written back transposed: new G[b][k] = point k of row b, the
 // second half taken mirrored (a3, m23, m123, m).
-__device__ __forceinline__ void take_half(const Split1& s, bool second, float g[4][4]) {
+__device__ __forceinline__ void take_half(const Row7 e[4], bool second, float g[4][4]) {
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    g[b][0] = second ? s.e[b].v[6] : s.e[b].v[0];
-    g[b][1] = second ? s.e[b].v[5] : s.e[b].v[1];
-    g[b][2] = second ? s.e[b].v[4] : s.e[b].v[2];
-    g[b][3] = s.e[b].v[3];
+    g[b][0] = second ? e[b].v[6] : e[b].v[0];
+    g[b][1] = second ? e[b].v[5] : e[b].v[1];
+    g[b][2] = second ? e[b].v[4] : e[b].v[2];
+    g[b][3] = e[b].v[3];
   }
 }
 

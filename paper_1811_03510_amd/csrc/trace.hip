@@ -42,12 +42,6 @@ constexpr int kStack = 48;
 
 enum Mode : int { kFetch = 0, kTraverse = 1, kStep = 2, kGrid = 3, kDead = 4 };
 
-struct Best {
-  float t;
-  uint32_t id;
-  float u, v;
-};
-
 struct Counts {
   uint32_t node, cand, split, backtrack, greg, leaf, crop, cand_greg;
 };
@@ -61,16 +55,30 @@ __device__ __forceinline__ float safe_inv(float d) {
   return d == 0.0f ? copysignf(1e30f, d) : __frcp_rn(d);
 }
 
+// Batch of launch ray k (a wave-uniform scan: the table is never indexed per lane).
+__device__ __forceinline__ uint32_t batch_of(const BatchTable& bt, uint32_t k) {
+  uint32_t b = 0;
+  for (uint32_t q = 1; q < bt.n_batches; ++q) b = k >= bt.prefix[q] ? q : b;
+  return b;
+}
+
 template <bool kStats>
-__device__ __forceinline__ void write_hit(ccs_hit* __restrict__ hits, uint32_t* __restrict__ counters, uint32_t rid,
-                                          const Best& best, const Counts& cnt) {
-  const bool hit = best.id != kNoHit;
+__device__ __forceinline__ void write_hit(const BatchTable& bt, uint32_t* __restrict__ counters, uint32_t rid,
+                                          float best_t, uint32_t best_id, float u, float v, const Counts& cnt) {
+  const bool hit = best_id != kNoHit;
   float4 h;
-  h.x = hit ? best.t : __builtin_inff();
-  h.y = __uint_as_float(best.id);
-  h.z = hit ? best.u : 0.0f;
-  h.w = hit ? best.v : 0.0f;
-  reinterpret_cast<float4*>(hits)[rid] = h;
+  h.x = hit ? best_t : __builtin_inff();
+  h.y = __uint_as_float(best_id);
+  h.z = hit ? u : 0.0f;
+  h.w = hit ? v : 0.0f;
+  ccs_hit* hits = bt.hits[0];
+  uint32_t local = rid;
+  for (uint32_t q = 1; q < bt.n_batches; ++q)
+    if (rid >= bt.prefix[q]) {
+      hits = bt.hits[q];
+      local = rid - bt.prefix[q];
+    }
+  reinterpret_cast<float4*>(hits)[local] = h;
   if (kStats) {
     uint4* c = reinterpret_cast<uint4*>(counters + 8 * (size_t)rid);
     c[0] = make_uint4(cnt.node, cnt.cand, cnt.split, cnt.backtrack);
@@ -79,26 +87,28 @@ __device__ __forceinline__ void write_hit(ccs_hit* __restrict__ hits, uint32_t* 
 }
 
 template <bool kStats>
-__global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* __restrict__ rays, uint32_t n,
-                                                  ccs_hit* __restrict__ hits, uint32_t* __restrict__ counters,
+__global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
                                                   LaunchParams lp) {
   __shared__ int stack[kStack * kBlock];
+  __shared__ float s_dir[3][kBlock];  // world direction: read only when a candidate is set up
+  __shared__ float s_uv[2][kBlock];   // (u, v) of the best hit: written only by leaf records
   const int lane = threadIdx.x;
   const int L2 = 2 * s.leaf_depth;
   const float leaf_scale = __uint_as_float((uint32_t)(127 - s.leaf_depth) << 23);  // 2^-L
 
+  const uint32_t n = bt.prefix[bt.n_batches];
   int mode = kFetch;
   uint32_t rid = 0;
+  const float4* nodes = s.nodes;  // the current ray's frame
+  const float* recs = s.recs;
   RayP wr = {0, 0, 0, 0, 0, 0, 0};  // world frame
-  RayP pr = {0, 0, 0, 0, 0, 0, 0};  // frame of the current patch (see the candidate set-up)
-  float wdx = 0.0f, wdy = 0.0f, wdz = 0.0f;  // world direction
-  float pt0 = 0.0f;                          // ray parameter of the patch frame's origin
-  Best best = {0.0f, kNoHit, 0.0f, 0.0f};
+  float pox = 0.0f, poy = 0.0f, poz = 0.0f, ptmin = 0.0f;  // origin and tmin in the current patch frame
+  float pt0 = 0.0f;                                         // ray parameter of the patch frame's origin
+  float best_t = 0.0f;
+  uint32_t best_id = kNoHit;
   Counts cnt = {0, 0, 0, 0, 0, 0, 0, 0};
   int cur = 0, sp = 0;
-  const float* rec = s.recs;
-  uint32_t pid = 0;
-  bool greg = false;
+  uint32_t rec_idx = 0, pmeta = 0;  // current patch record and its meta bits (index | Gregory bit)
   Grid G;
   float dx = 0.0f, dy = 0.0f, dz = 0.0f;
   uint32_t code = 0, trail = 0, mirror = 0;
@@ -122,18 +132,28 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
         if (rid >= n) {
           mode = kDead;
         } else {
-          const float4* r4 = reinterpret_cast<const float4*>(rays + rid);
+          const ccs_ray* rays = bt.rays[0];
+          uint32_t local = rid, frame = bt.frame[0];
+          for (uint32_t q = 1; q < bt.n_batches; ++q)
+            if (rid >= bt.prefix[q]) {
+              rays = bt.rays[q];
+              local = rid - bt.prefix[q];
+              frame = bt.frame[q];
+            }
+          nodes = s.nodes + (size_t)frame * s.frame_node_f4;
+          recs = s.recs + (size_t)frame * s.frame_rec_floats;
+          const float4* r4 = reinterpret_cast<const float4*>(rays + local);
           const float4 ro = r4[0], rd = r4[1];
           // integer bit tests: this file is compiled assuming no NaN
           const bool finite = finite_bits(ro.x) && finite_bits(ro.y) && finite_bits(ro.z) && finite_bits(rd.x) &&
                               finite_bits(rd.y) && finite_bits(rd.z) && !nan_bits(ro.w) && !nan_bits(rd.w);
           const bool valid = finite && !(rd.x == 0.0f && rd.y == 0.0f && rd.z == 0.0f) && ro.w <= rd.w &&
                              s.n_nodes > 0;
-          best.t = rd.w;
-          best.id = kNoHit;
+          best_t = rd.w;
+          best_id = kNoHit;
           if (kStats) cnt = Counts{0, 0, 0, 0, 0, 0, 0, 0};
           if (!valid) {
-            write_hit<kStats>(hits, counters, rid, best, cnt);
+            write_hit<kStats>(bt, counters, rid, best_t, best_id, 0.0f, 0.0f, cnt);
           } else {
             wr.ox = ro.x;
             wr.oy = ro.y;
@@ -142,12 +162,9 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
             wr.iy = safe_inv(rd.y);
             wr.iz = safe_inv(rd.z);
             wr.tmin = ro.w;
-            wdx = rd.x;
-            wdy = rd.y;
-            wdz = rd.z;
-            pr.ix = wr.ix;
-            pr.iy = wr.iy;
-            pr.iz = wr.iz;
+            s_dir[0][lane] = rd.x;
+            s_dir[1][lane] = rd.y;
+            s_dir[2][lane] = rd.z;
             cur = 0;
             sp = 0;
             mode = kTraverse;
@@ -159,29 +176,31 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
 
     // ------------------------------------------- traverse to the next candidate
     if (mt != 0 && ((uint32_t)__popcll(mt) >= lp.traverse_min || (ms | mg) == 0)) {
-      while (mode == kTraverse) {
+      // at most traverse_steps node visits per phase: lanes still walking keep their
+      // place and continue next time, so one lane's long walk does not hold the wave
+      for (uint32_t it = 0; mode == kTraverse && it < lp.traverse_steps; ++it) {
         if (cur < 0) {  // candidate patch: set up Alg. 3 at the root
           if (kStats) cnt.cand++;
-          rec = s.recs + (size_t)(~cur) * kRecFloats;
+          rec_idx = (uint32_t)(~cur);
+          const float* rec = recs + (size_t)rec_idx * kRecFloats;
           const float4 meta = reinterpret_cast<const float4*>(rec)[15];
-          const uint32_t mbits = __float_as_uint(meta.w);
-          greg = (mbits & kGregoryBit) != 0;
-          pid = mbits & kIdMask;
+          pmeta = __float_as_uint(meta.w);
           // Patch frame: anchored at the patch's anchor, origin moved along the ray to
           // (about) the point closest to the anchor, computed in double and rounded
           // once.  Distances inside the patch are then of the patch's size, so their
           // rounding, and the conservative widening of the slab test that covers it,
           // are relative to the patch rather than to the distance from the ray
           // origin (Sec. 3.4: anchoring for precision).  Any t0 gives the same ray.
+          const float wdx = s_dir[0][lane], wdy = s_dir[1][lane], wdz = s_dir[2][lane];
           const float qx = meta.x - wr.ox, qy = meta.y - wr.oy, qz = meta.z - wr.oz;
           pt0 = (qx * wdx + qy * wdy + qz * wdz) * __builtin_amdgcn_rcpf(wdx * wdx + wdy * wdy + wdz * wdz);
-          pr.ox = (float)fma((double)pt0, (double)wdx, (double)wr.ox - (double)meta.x);
-          pr.oy = (float)fma((double)pt0, (double)wdy, (double)wr.oy - (double)meta.y);
-          pr.oz = (float)fma((double)pt0, (double)wdz, (double)wr.oz - (double)meta.z);
-          pr.tmin = (float)((double)wr.tmin - (double)pt0);
+          pox = (float)fma((double)pt0, (double)wdx, (double)wr.ox - (double)meta.x);
+          poy = (float)fma((double)pt0, (double)wdy, (double)wr.oy - (double)meta.y);
+          poz = (float)fma((double)pt0, (double)wdz, (double)wr.oz - (double)meta.z);
+          ptmin = (float)((double)wr.tmin - (double)pt0);
           code = trail = mirror = 0;
           depth = 0;
-          if (greg) {
+          if (pmeta & kGregoryBit) {
             if (kStats) cnt.cand_greg++;
             mode = kGrid;
           } else {
@@ -196,11 +215,11 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
           break;
         }
         if (kStats) cnt.node++;
-        const float4* nd = s.nodes + 4 * (size_t)cur;
+        const float4* nd = nodes + 4 * (size_t)cur;
         const float4 a = nd[0], b = nd[1], c = nd[2], e = nd[3];
         const int c0 = __float_as_int(e.x), c1 = __float_as_int(e.y);
-        const float t0 = slab(wr, a.x, a.y, a.z, a.w, b.x, b.y, best.t);
-        const float t1 = slab(wr, b.z, b.w, c.x, c.y, c.z, c.w, best.t);
+        const float t0 = slab(wr, a.x, a.y, a.z, a.w, b.x, b.y, best_t);
+        const float t1 = slab(wr, b.z, b.w, c.x, c.y, c.z, c.w, best_t);
         const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
         if (h0 && h1) {
           const bool first1 = t1 < t0;
@@ -216,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
           --sp;
           cur = stack[sp * kBlock + lane];
         } else {
-          write_hit<kStats>(hits, counters, rid, best, cnt);
+          write_hit<kStats>(bt, counters, rid, best_t, best_id, s_uv[0][lane], s_uv[1][lane], cnt);
           mode = kFetch;
         }
       }
@@ -232,8 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
         const float v0 = (float)compact_even(code) * leaf_scale;
         const float su = __uint_as_float((uint32_t)(127 - ((depth + 1) >> 1)) << 23);
         const float sv = __uint_as_float((uint32_t)(127 - (depth >> 1)) << 23);
+        const bool greg = (pmeta & kGregoryBit) != 0;
         PatchPts P;
-        load_grid(rec, P, greg);
+        load_grid(recs + (size_t)rec_idx * kRecFloats, P, greg);
         float qx[4][4], qy[4][4], qz[4][4];
         calc_points_and_d(P, greg, u0, u0 + su, v0, v0 + sv, qx, qy, qz, dx, dy, dz);
         const bool along_v = (depth & 1) != 0;
@@ -254,42 +274,48 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
     // -------------------------------------------------- one subdivision step
     if (mode == kStep) {
       if (kStats) cnt.split++;
-      const Split1 sx = split_component(G.x);
-      const Split1 sy = split_component(G.y);
-      const Split1 sz = split_component(G.z);
-      const float cap = best.t - pt0;  // the best distance in the patch frame
-      const float ta = slab(pr, sx.lo_a, sy.lo_a, sz.lo_a, sx.hi_a + dx, sy.hi_a + dy, sz.hi_a + dz, cap);
-      const float tb = slab(pr, sx.lo_b, sy.lo_b, sz.lo_b, sx.hi_b + dx, sy.hi_b + dy, sz.hi_b + dz, cap);
-      const bool ha = ta != __builtin_inff(), hb = tb != __builtin_inff();
+      // split each component and fold its two child boxes into the slab test at once
+      Row7 ex[4], ey[4], ez[4];
+      SlabPair sp2 = {ptmin, __builtin_inff(), ptmin, __builtin_inff()};
+      split_fold(G.x, pox, wr.ix, dx, ex, sp2);
+      split_fold(G.y, poy, wr.iy, dy, ey, sp2);
+      split_fold(G.z, poz, wr.iz, dz, ez, sp2);
+      const float cap = best_t - pt0;  // the best distance in the patch frame
+      const float fa = fminf(sp2.fa * kFarScale, cap), fb = fminf(sp2.fb * kFarScale, cap);
+      const bool ha = sp2.na <= fa, hb = sp2.nb <= fb;
+      const float ta = sp2.na, tb = sp2.nb;
       const int axis = depth & 1;
       const bool mir = ((mirror >> axis) & 1u) != 0;
       const bool h_lo = mir ? hb : ha, h_up = mir ? ha : hb;
       const float t_lo = mir ? tb : ta, t_up = mir ? ta : tb;
       const bool go_up = h_up && (!h_lo || t_up < t_lo);
       const uint32_t bit = 1u << (L2 - 1 - depth);
+      // the chosen half replaces the grid on every path: when the lane backtracks or
+      // leaves the patch instead, the grid is rebuilt before it is read again
+      const bool second = go_up != mir;
+      take_half(ex, second, G.x);
+      take_half(ey, second, G.y);
+      take_half(ez, second, G.z);
       bool backtrack = !(ha || hb);
       if (!backtrack) {
         if (depth == L2 - 1) {
           const float tf = pt0 + (go_up ? t_up : t_lo);
-          if (tf < best.t || (tf == best.t && pid < best.id)) {
+          const uint32_t pid = pmeta & kIdMask;
+          if (tf < best_t || (tf == best_t && pid < best_id)) {
             const uint32_t lc = code | (go_up ? bit : 0u);
-            best.t = tf;
-            best.id = pid;
-            best.u = (float)(2u * compact_even(lc >> 1) + 1u) * (0.5f * leaf_scale);
-            best.v = (float)(2u * compact_even(lc) + 1u) * (0.5f * leaf_scale);
+            best_t = tf;
+            best_id = pid;
+            s_uv[0][lane] = (float)(2u * compact_even(lc >> 1) + 1u) * (0.5f * leaf_scale);
+            s_uv[1][lane] = (float)(2u * compact_even(lc) + 1u) * (0.5f * leaf_scale);
             if (kStats) cnt.leaf++;
           }
           backtrack = true;
         } else {
           if (ha && hb) trail |= bit;
           if (go_up) code |= bit;
-          const bool second = go_up != mir;
-          take_half(sx, second, G.x);
-          take_half(sy, second, G.y);
-          take_half(sz, second, G.z);
           if (second) mirror ^= (1u << axis);
           depth++;
-          if (greg) mode = kGrid;  // Alg. 3 recomputes a Gregory grid at every node
+          if (pmeta & kGregoryBit) mode = kGrid;  // Alg. 3 recomputes a Gregory grid at every node
         }
       }
       if (backtrack) {
@@ -306,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, const ccs_ray* 
           cur = stack[sp * kBlock + lane];
           mode = kTraverse;
         } else {  // ray done
-          write_hit<kStats>(hits, counters, rid, best, cnt);
+          write_hit<kStats>(bt, counters, rid, best_t, best_id, s_uv[0][lane], s_uv[1][lane], cnt);
           mode = kFetch;
         }
       }
@@ -329,8 +355,9 @@ static int resident_waves_per_cu() {
 
 int max_waves_per_cu(bool counted) { return counted ? resident_waves_per_cu<true>() : resident_waves_per_cu<false>(); }
 
-hipError_t launch_intersect(const DeviceScene& s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, uint32_t* counters,
-                            const LaunchParams& lp, uint32_t waves_per_cu, hipStream_t stream) {
+hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
+                            uint32_t waves_per_cu, hipStream_t stream) {
+  const uint32_t n = bt.prefix[bt.n_batches];
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, stream, lp.queue);
   int per_cu = max_waves_per_cu(counters != nullptr);
@@ -339,9 +366,9 @@ hipError_t launch_intersect(const DeviceScene& s, const ccs_ray* rays, uint32_t 
   const uint32_t needed = (n + kBlock - 1) / kBlock;
   const dim3 grid(std::min(waves, needed)), block(kBlock);
   if (counters)
-    hipLaunchKernelGGL(k_trace<true>, grid, block, 0, stream, s, rays, n, hits, counters, lp);
+    hipLaunchKernelGGL(k_trace<true>, grid, block, 0, stream, s, bt, counters, lp);
   else
-    hipLaunchKernelGGL(k_trace<false>, grid, block, 0, stream, s, rays, n, hits, nullptr, lp);
+    hipLaunchKernelGGL(k_trace<false>, grid, block, 0, stream, s, bt, nullptr, lp);
   return hipGetLastError();
 }
 

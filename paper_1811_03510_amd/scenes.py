@@ -377,3 +377,59 @@ def sample_indices(n: int, k: int, seed: int = SEED) -> np.ndarray:
     """A seeded sorted sample of k distinct indices out of n (k <= n)."""
     k = min(k, n)
     return choose(seed, n, k)
+
+
+# -------------------------------------------------------------- animation
+def animate(cp: np.ndarray, frame: int, n_frames: int = 16, seed: int = STREAM_ANIMATION,
+            amp_rel: float = 0.05) -> np.ndarray:
+    """Frame ``frame`` of a seeded animation: every control point x (all 20 slots) moves by
+    A (sin(k1.x + 2 pi f/F + p1), sin(k2.x + 2 pi f/F + p2), sin(k3.x + 2 pi f/F + p3)),
+    A = amp_rel * mean patch cell, k_i = 2 pi * seeded unit vectors, p_i seeded.  The
+    displacement is a function of the rest position, so points shared by neighbouring
+    patches move together and seams stay closed."""
+    s = [substream(seed, k) for k in range(2)]
+    k = normal(s[0], 9).reshape(3, 3)
+    k = 2.0 * np.pi * k / np.linalg.norm(k, axis=1, keepdims=True)
+    phase = 2.0 * np.pi * uniform(s[1], 3)
+    c = cp.astype(np.float64)
+    amp = amp_rel * float(np.mean(patch_cell(c[:, :16])))
+    x = c.reshape(-1, 3)
+    arg = x @ k.T + phase[None, :] + 2.0 * np.pi * frame / n_frames
+    return (x + amp * np.sin(arg)).reshape(cp.shape).astype(np.float32)
+
+
+@dataclasses.dataclass
+class Animation:
+    name: str
+    cp0: np.ndarray
+    types: np.ndarray
+    leaf_depth: int
+    frames: list          # per frame: control points (n, 20, 3) float32
+    rays: list            # per frame: (N_f, 8) float32, primary rays first
+    n_primary: list       # per frame: number of primary rays at the front of rays[f]
+
+    @property
+    def diameter(self) -> float:
+        c = self.cp0.reshape(-1, 3).astype(np.float64)
+        return float(np.linalg.norm(c.max(axis=0) - c.min(axis=0)))
+
+
+def config3(n_frames: int = 16, lo: int = 1 << 16, hi: int = 1 << 21, seed: int = STREAM_BATCH) -> Animation:
+    """The 512-patch torus animated over n_frames frames; per frame a log-uniform
+    number of rays in [lo, hi]: half primary from an orbiting camera (square image),
+    half secondary rays from that frame's surface."""
+    cp0, types = torus_scene()
+    sizes = np.round(np.exp(np.log(lo) + (np.log(hi) - np.log(lo)) * uniform(seed, n_frames))).astype(np.int64)
+    frames, rays, n_prim = [], [], []
+    for f in range(n_frames):
+        cp = animate(cp0, f, n_frames)
+        ang = 2.0 * np.pi * f / n_frames
+        eye = (3.2 * np.sin(ang), -3.2 * np.cos(ang), 2.0)
+        side = max(8, int(round(np.sqrt(sizes[f] / 2))))
+        prim = pinhole_rays(eye, (0, 0, 0), (0, 0, 1), 40.0, side, side)
+        diff = surface_bounce_rays(cp, types, 12, eye, int(max(0, sizes[f] - side * side)),
+                                   seed=substream(STREAM_BOUNCE, 100 + f))
+        frames.append(cp)
+        rays.append(np.concatenate([prim, diff]))
+        n_prim.append(len(prim))
+    return Animation(f"torus512-anim{n_frames}", cp0, types, 12, frames, rays, n_prim)

@@ -1,0 +1,116 @@
+"""Frames, batched launches and HIP-graph replay (animation playback): hits of a
+batched launch equal single-batch launches of the same rays bitwise, each frame
+matches the oracle on that frame's geometry, and a captured frame loop replays
+to the eager result every time."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.parity import assert_gate, gate
+from paper_1811_03510_amd import scenes as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def anim():
+    return S.config3(n_frames=4, lo=1 << 10, hi=1 << 14)
+
+
+@pytest.fixture(scope="module")
+def scene(anim):
+    from paper_1811_03510_amd import ccs
+    g = ccs.Scene(torch.from_numpy(anim.cp0).cuda(), torch.from_numpy(anim.types).cuda(), anim.leaf_depth)
+    g.set_frames(len(anim.frames))
+    for f, cp in enumerate(anim.frames):
+        g.refit_frame(f, torch.from_numpy(cp).cuda())
+    torch.cuda.synchronize()
+    return g
+
+
+def test_frames_match_the_oracle(anim, scene):
+    for f, (cp, rays) in enumerate(zip(anim.frames, anim.rays)):
+        _say(f"frame {f}: {len(rays)} rays")
+        (h,) = scene.intersect_batched([(f, torch.from_numpy(rays).cuda(), None)])
+        torch.cuda.synchronize()
+        osc = O.Scene(cp, anim.types, anim.leaf_depth)
+        assert_gate(gate(h.cpu().numpy(), osc.intersect(rays), rays, osc, anim.diameter, anim.leaf_depth,
+                         label=f"anim-frame{f}"))
+
+
+def test_batched_launch_equals_single_batches(anim, scene):
+    rng = np.random.default_rng(9)
+    parts = []
+    for f, rays in enumerate(anim.rays):
+        cut = np.sort(rng.choice(len(rays), size=3, replace=False))
+        for a, b in zip([0, *cut], [*cut, len(rays)]):
+            parts.append((f, rays[a:b]))
+    parts.append((1, anim.rays[1][:0]))  # an empty batch
+    rng.shuffle(parts)
+    parts = parts[:32]
+    dev = [(f, torch.from_numpy(np.ascontiguousarray(r)).cuda(), None) for f, r in parts]
+    _say(f"batched launch of {len(dev)} batches")
+    many = scene.intersect_batched(dev)
+    singles = [scene.intersect_batched([d])[0] for d in dev]
+    torch.cuda.synchronize()
+    for a, b in zip(many, singles):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+
+
+def test_frame0_batch_equals_intersect(anim, scene):
+    r = torch.from_numpy(anim.rays[0]).cuda()
+    a = scene.intersect(r)
+    (b,) = scene.intersect_batched([(0, r, None)])
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+
+
+def test_batch_limits(anim, scene):
+    from paper_1811_03510_amd import ccs
+    r = torch.from_numpy(anim.rays[0][:10]).cuda()
+    with pytest.raises(ccs.CcsError):
+        scene.intersect_batched([(0, r, None)] * 33)
+    with pytest.raises(ccs.CcsError):
+        scene.intersect_batched([(len(anim.frames), r, None)])
+
+
+def test_graph_captured_frame_loop_replays(anim, scene):
+    """[refit every frame -> one batched launch] captured once, replayed three times
+    with eager work and synchronizations between the replays."""
+    cps = [torch.from_numpy(cp).cuda() for cp in anim.frames]
+    rays = [torch.from_numpy(r).cuda() for r in anim.rays]
+    hits = [torch.empty((r.shape[0], 4), dtype=torch.float32, device="cuda") for r in rays]
+    batches = [(f, rays[f], hits[f]) for f in range(len(rays))]
+
+    def loop():
+        for f, cp in enumerate(cps):
+            scene.refit_frame(f, cp)
+        scene.intersect_batched(batches)
+
+    loop()
+    torch.cuda.synchronize()
+    eager = [h.cpu().numpy().copy() for h in hits]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        loop()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        loop()
+    for rep in range(3):
+        for h in hits:
+            h.fill_(-1.0)
+        x = torch.randn(1 << 20, device="cuda")  # eager work between replays
+        (x * 2).sum().item()
+        _say(f"graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        for e, h in zip(eager, hits):
+            assert np.array_equal(e.view(np.uint32), h.cpu().numpy().view(np.uint32))

@@ -64,10 +64,10 @@ def test_launch_configuration_never_changes_results(ccs, c1, c1_gpu):
     rays = np.concatenate([c1.primary, c1.diffuse])
     c1_gpu.set_launch()
     base = run(c1_gpu, rays)
-    for w, f, t, g in ((1, 1, 1, 1), (0, 64, 64, 64), (2, 8, 32, 4), (0, 1, 64, 1), (3, 33, 2, 64)):
-        _say(f"launch waves/CU={w} fetch>={f} traverse>={t} grid>={g}")
-        c1_gpu.set_launch(w, f, t, g)
-        assert np.array_equal(run(c1_gpu, rays).view(np.uint32), base.view(np.uint32)), (w, f, t, g)
+    for w, f, t, g, k in ((1, 1, 1, 1, 0), (0, 64, 64, 64, 1), (2, 8, 32, 4, 3), (0, 1, 64, 1, 0), (3, 33, 2, 64, 7)):
+        _say(f"launch waves/CU={w} fetch>={f} traverse>={t} grid>={g} steps={k}")
+        c1_gpu.set_launch(w, f, t, g, k)
+        assert np.array_equal(run(c1_gpu, rays).view(np.uint32), base.view(np.uint32)), (w, f, t, g, k)
     c1_gpu.set_launch()
     with pytest.raises(ccs.CcsError):
         c1_gpu.set_launch(0, 0, 16, 16)
