@@ -433,3 +433,28 @@ def config3(n_frames: int = 16, lo: int = 1 << 16, hi: int = 1 << 21, seed: int 
         rays.append(np.concatenate([prim, diff]))
         n_prim.append(len(prim))
     return Animation(f"torus512-anim{n_frames}", cp0, types, 12, frames, rays, n_prim)
+
+
+# --------------------------------------------------- child-ordering network
+N_POLICY_PARAMS = 1732  # 16 -> 32 -> 32 -> 4: W1 (32x16), b1, W2 (32x32), b2, W3 (4x32), b3
+
+
+def mlp_init(seed: int = STREAM_MLP) -> np.ndarray:
+    """Seeded initial weights, fp32, flat in the order W1, b1, W2, b2, W3, b3:
+    weights uniform in +-sqrt(6 / fan_in) (He et al. 2015), biases zero."""
+    shapes = ((32, 16), (32,), (32, 32), (32,), (4, 32), (4,))
+    out = []
+    for k, shp in enumerate(shapes):
+        if len(shp) == 1:
+            out.append(np.zeros(shp))
+        else:
+            lim = np.sqrt(6.0 / shp[1])
+            out.append((2.0 * uniform(substream(seed, k), int(np.prod(shp))) - 1.0) * lim)
+    return np.concatenate([o.reshape(-1) for o in out]).astype(np.float32)
+
+
+def policy_training_rays(n: int, seed: int = STREAM_MLP) -> np.ndarray:
+    """Secondary rays on the 512-patch torus for recording ordering traces: the
+    same recipe as its diffuse workload, from a stream of their own."""
+    cp, types = torus_scene()
+    return surface_bounce_rays(cp, types, 12, (0.0, -3.2, 2.0), n, seed=substream(seed, 100))
