@@ -6,10 +6,12 @@ Workload (default): 1,000,000 patches (2000 seeded displaced tori / apple tori,
 ray per pixel (cosine-weighted bounce from seeded surface points).  Synthetic,
 seeded, generated on the host and resident in HBM before timing starts.
 
-A step is one intersection launch over all primary rays followed by one over
-all secondary rays (the whole hot path per batch).  W warm-up steps, then K
-steps timed with HIP events recorded on the stream the kernels run on.  Prints
-one JSON line.  The CPU baseline times the FP64 oracle on a bounded seeded
+A step is one pass over all primary and all secondary rays.  Two variants are
+timed: "plain" (one launch per ray class, the library's default launch
+parameters) and "batched" (both classes as two batches of one launch, launch
+parameters from the autotuner); `value` is the batched one.  W warm-up steps,
+then K steps timed with HIP events recorded on the stream the kernels run on.
+Prints one JSON line.  The CPU baseline times the FP64 oracle on a bounded seeded
 sample of the same rays on the host cores and reports the parity of that sample.
 """
 from __future__ import annotations
@@ -88,11 +90,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["instanced1m", "torus512"], default="instanced1m")
+    ap.add_argument("--workload", choices=["instanced1m", "torus512", "anim512"], default="instanced1m",
+                    help="anim512: the 512-patch torus animated over 16 frames, every frame refit and all "
+                         "frames' uneven ray batches in one launch, the frame loop replayed as a HIP graph")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-counters", action="store_true", help="skip the counted launch (roofline)")
-    ap.add_argument("--launch", default="", help="waves_per_cu,fetch_min,traverse_min,grid_min (default: library's)")
+    ap.add_argument("--launch", default="",
+                    help="waves_per_cu,fetch_min,traverse_min,grid_min,traverse_steps (default: library's)")
+    ap.add_argument("--only", choices=["", "plain", "batched"], default="",
+                    help="time one variant only (a profiler run then sees one launch shape)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batched variant with the given/default launch instead of the tuned one")
+    ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer once (a plain copy kernel of known size that "
                          "scales the profiler's FETCH_SIZE / WRITE_SIZE)")
@@ -117,6 +127,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del src, dst
+    if args.workload == "anim512":
+        return bench_animation(args, torch, ccs, scenes)
     t0 = time.time()
     w = scenes.config2() if args.workload == "instanced1m" else scenes.config1()
     gen_s = time.time() - t0
@@ -135,11 +147,14 @@ def main():
 
     prim = torch.from_numpy(w.primary).cuda()
     diff = torch.from_numpy(w.diffuse).cuda()
-    hp = torch.empty((prim.shape[0], 4), dtype=torch.float32, device="cuda")
-    hd = torch.empty((diff.shape[0], 4), dtype=torch.float32, device="cuda")
+    n_p, n_d = prim.shape[0], diff.shape[0]
+    hp = torch.empty((n_p, 4), dtype=torch.float32, device="cuda")
+    hd = torch.empty((n_d, 4), dtype=torch.float32, device="cuda")
+    hbp, hbd = torch.empty_like(hp), torch.empty_like(hd)
     stream = torch.cuda.current_stream()
+    batches = [(0, prim, hbp), (0, diff, hbd)]
 
-    def step(evs=None):
+    def plain_step(evs=None):
         if evs:
             evs[0].record(stream)
         scene.intersect(prim, hp)
@@ -149,32 +164,62 @@ def main():
         if evs:
             evs[2].record(stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    tp = np.array([e[0].elapsed_time(e[1]) for e in events])
-    td = np.array([e[1].elapsed_time(e[2]) for e in events])
-    total_ms = events[0][0].elapsed_time(events[-1][2])
-    ms_step = total_ms / args.steps
-    n_p, n_d = prim.shape[0], diff.shape[0]
-    value = (n_p + n_d) / (ms_step * 1e-3) / 1e6
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, primary {np.median(tp):.3f} ms, "
-        f"secondary {np.median(td):.3f} ms -> {value:.1f} MRays/s")
+    def batched_step(evs=None):
+        if evs:
+            evs[0].record(stream)
+        scene.intersect_batched(batches)
+        if evs:
+            evs[1].record(stream)
 
-    hits_p, hits_d = hp.cpu().numpy(), hd.cpu().numpy()
-    per_class = {
-        "primary": {"rays": n_p, "ms_median": float(np.median(tp)), "ms_p10": float(np.percentile(tp, 10)),
-                    "ms_p90": float(np.percentile(tp, 90)), "mrays_per_s": n_p / np.median(tp) / 1e3,
-                    "hit_fraction": float((ccs.hit_ids(hits_p) != ccs.NO_HIT).mean())},
-        "diffuse": {"rays": n_d, "ms_median": float(np.median(td)), "ms_p10": float(np.percentile(td, 10)),
-                    "ms_p90": float(np.percentile(td, 90)), "mrays_per_s": n_d / np.median(td) / 1e3,
-                    "hit_fraction": float((ccs.hit_ids(hits_d) != ccs.NO_HIT).mean())},
-    }
+    def timed(step, n_events):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(n_events)] for _ in range(args.steps)]
+        for k in range(args.steps):
+            step(events[k])
+        torch.cuda.synchronize()
+        laps = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(n_events - 1)] for e in events])
+        return laps, events[0][0].elapsed_time(events[-1][-1]) / args.steps
+
+    def cls(n, t, hits):
+        return {"rays": n, "ms_median": float(np.median(t)), "ms_p10": float(np.percentile(t, 10)),
+                "ms_p90": float(np.percentile(t, 90)), "mrays_per_s": n / np.median(t) / 1e3,
+                "hit_fraction": float((ccs.hit_ids(hits) != ccs.NO_HIT).mean())}
+
+    variants = {}
+    if args.only in ("", "plain"):
+        laps, ms = timed(plain_step, 3)
+        tp, td = laps[:, 0], laps[:, 1]
+        hits_p, hits_d = hp.cpu().numpy(), hd.cpu().numpy()
+        variants["plain"] = {
+            "ms_per_step": ms, "mrays_per_s": (n_p + n_d) / (ms * 1e-3) / 1e6, "launch": dict(launch),
+            "launches_per_step": 2, "kernel_ms": float(np.mean(laps)),
+            "per_class": {"primary": cls(n_p, tp, hits_p), "diffuse": cls(n_d, td, hits_d)}}
+        log(f"plain: {ms:.3f} ms/step, primary {np.median(tp):.3f} ms, secondary {np.median(td):.3f} ms "
+            f"-> {variants['plain']['mrays_per_s']:.1f} MRays/s")
+    if args.only in ("", "batched"):
+        if args.autotune:
+            from paper_1811_03510_amd import autotune
+            t0 = time.time()
+            tuned = autotune.tuned(scene, batches, name=w.name, log=log if args.verbose else None)
+            log(f"autotuned launch {tuned} in {time.time() - t0:.1f} s")
+        laps, ms = timed(batched_step, 2)
+        hits_p, hits_d = hbp.cpu().numpy(), hbd.cpu().numpy()
+        variants["batched"] = {
+            "ms_per_step": ms, "mrays_per_s": (n_p + n_d) / (ms * 1e-3) / 1e6, "launch": scene.get_launch(),
+            "launches_per_step": 1, "kernel_ms": float(np.mean(laps)), "autotuned": bool(args.autotune),
+            "ms_median": float(np.median(laps)), "ms_p10": float(np.percentile(laps, 10)),
+            "ms_p90": float(np.percentile(laps, 90))}
+        if "plain" in variants:
+            variants["batched"]["bitwise_equal_to_plain"] = bool(
+                np.array_equal(hits_p.view(np.uint32), hp.cpu().numpy().view(np.uint32))
+                and np.array_equal(hits_d.view(np.uint32), hd.cpu().numpy().view(np.uint32)))
+        log(f"batched: {ms:.3f} ms/step -> {variants['batched']['mrays_per_s']:.1f} MRays/s "
+            f"(launch {variants['batched']['launch']})")
+    head = "batched" if "batched" in variants else "plain"
+    ms_step = variants[head]["ms_per_step"]
+    value = variants[head]["mrays_per_s"]
 
     roofline = None
     work = None
@@ -184,14 +229,16 @@ def main():
         torch.cuda.synchronize()
         cp_, cd_ = cp_.cpu().numpy(), cd_.cpu().numpy()
         ops_p, ops_d = algorithmic_ops(cp_), algorithmic_ops(cd_)
-        launch_ms = float(np.mean(tp) + np.mean(td)) / 2.0
-        achieved = (ops_p + ops_d) / ((np.mean(tp) + np.mean(td)) * 1e-3) / 1e12
+        per_launch = variants[head]["launches_per_step"]
+        launch_ms = variants[head]["kernel_ms"]
+        ops_launch = (ops_p + ops_d) / per_launch
+        achieved = ops_launch / (launch_ms * 1e-3) / 1e12
         bytes_launch = traffic_from_profiles(launch_ms)
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
                     "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
                     "traffic": bytes_launch, "kernel": "k_trace<false>",
                     "kernel_avg_ms": round(launch_ms, 4),
-                    "ops_per_launch": (ops_p + ops_d) / 2.0,
+                    "ops_per_launch": ops_launch,
                     "ops_per_ray": {"primary": ops_p / n_p, "diffuse": ops_d / n_d}}
         work = {c: {"primary": float(cp_[:, k].mean()), "diffuse": float(cd_[:, k].mean())}
                 for k, c in enumerate(COUNTERS)}
@@ -242,10 +289,11 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": (f"{w.name}: {w.cp.shape[0]} patches "
                                 f"({int(w.types.sum())} Gregory), {n_p} primary + {n_d} secondary rays per step"),
-                   "variant": "plain (closest-first order, one launch per ray class)",
-                   "launch": launch,
+                   "variant": {"plain": "closest-first order, one launch per ray class",
+                               "batched": "closest-first order, both ray classes in one autotuned launch"}[head],
+                   "launch": variants[head]["launch"],
                    "leaf_depth": w.leaf_depth},
-        "per_class": per_class,
+        "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
@@ -255,6 +303,90 @@ def main():
         "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_animation(args, torch, ccs, scenes):
+    """Batched animation playback: per step, refit all frames and intersect every
+    frame's rays in one launch; the step is captured once as a HIP graph and replayed."""
+    from paper_1811_03510_amd import autotune
+    t0 = time.time()
+    a = scenes.config3()
+    gen_s = time.time() - t0
+    nf = len(a.frames)
+    n_rays = sum(len(r) for r in a.rays)
+    log(f"workload {a.name}: {a.cp0.shape[0]} patches, {nf} frames, {n_rays} rays "
+        f"({[len(r) for r in a.rays]}), generated in {gen_s:.1f} s")
+    scene = ccs.Scene(torch.from_numpy(a.cp0).cuda(), torch.from_numpy(a.types).cuda(), a.leaf_depth)
+    scene.set_frames(nf)
+    cps = [torch.from_numpy(c).cuda() for c in a.frames]
+    rays = [torch.from_numpy(r).cuda() for r in a.rays]
+    hits = [torch.empty((r.shape[0], 4), dtype=torch.float32, device="cuda") for r in rays]
+    batches = [(f, rays[f], hits[f]) for f in range(nf)]
+
+    def frame_loop():
+        for f in range(nf):
+            scene.refit_frame(f, cps[f])
+        scene.intersect_batched(batches)
+
+    frame_loop()
+    torch.cuda.synchronize()
+    tuned = autotune.tuned(scene, batches, name=a.name, log=log if args.verbose else None) if args.autotune else None
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        frame_loop()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        frame_loop()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        graph.replay()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    laps = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    value = n_rays / (ms * 1e-3) / 1e6
+    log(f"animation: {ms:.3f} ms per replay of {nf} refits + one launch -> {value:.1f} MRays/s")
+
+    cpu, parity = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.parity import gate
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+        threads = min(threads, os.cpu_count() or threads)
+        per_frame = 4096
+        osec, ok, worst, nsamp = 0.0, True, 1.0, 0
+        for f in range(nf):
+            osc = oracle.Scene(a.frames[f], a.types, a.leaf_depth)
+            sel = scenes.sample_indices(len(a.rays[f]), min(per_frame, len(a.rays[f])), seed=200 + f)
+            t0 = time.time()
+            o = osc.intersect(a.rays[f][sel], nthreads=threads)
+            osec += time.time() - t0
+            nsamp += len(sel)
+            r = gate(hits[f].cpu().numpy()[sel], o, a.rays[f][sel], osc, a.diameter, a.leaf_depth,
+                     label=f"frame{f}")
+            ok, worst = ok and r["ok"], min(worst, r["id_rate"])
+        cpu = {"value": round(nsamp / osec / 1e6, 4), "unit": "MRays/s", "cores": threads, "kind": "oracle",
+               "sample": f"{per_frame} seeded rays per frame of the {nf} frames (oracle BVH builds excluded)"}
+        parity = {"frames": nf, "rays": nsamp, "ok": ok, "worst_frame_same_hit_and_patch": worst}
+        log(f"cpu baseline {cpu['value']} MRays/s; parity {parity}")
+    print(json.dumps({
+        "metric": "MRays/s batched animation playback (refit + intersect per frame, HIP graph replay)",
+        "value": round(value, 3), "unit": "MRays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded)",
+        "config": {"workload": f"{a.name}: {a.cp0.shape[0]} patches, {nf} frames, {n_rays} rays "
+                               f"(half primary, half secondary per frame)",
+                   "launch": scene.get_launch(), "autotuned": tuned is not None, "leaf_depth": a.leaf_depth,
+                   "ms_median": float(np.median(laps))},
+        "roofline": None, "cpu_baseline": cpu, "parity_sample": parity, "source_hash": source_hash()}),
+        flush=True)
 
 
 if __name__ == "__main__":

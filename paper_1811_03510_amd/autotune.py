@@ -1,0 +1,139 @@
+"""Launch-parameter autotuner for the persistent intersect kernel.
+
+The kernel's results never depend on its launch parameters (ray-to-lane
+assignment and phase order change only the schedule), so the tuner is free to
+pick whatever runs fastest.  It searches, by coordinate descent from the
+library defaults:
+
+  waves_per_cu     resident waves per compute unit (0 = as many as fit)
+  fetch_min        free lanes a wave waits for before it refills from the queue
+                   (the queue chunk: a refill takes exactly that many rays or more)
+  traverse_min     lanes in BVH traversal that trigger a traversal phase
+  grid_min         lanes waiting for a grid recompute that trigger that phase
+  traverse_steps   BVH nodes a lane visits per traversal phase
+
+timing the caller's workload (a list of batches for one ccs_intersect_batched
+call) with HIP events, median of a few repetitions.  The winner is cached in a
+JSON file keyed by GPU architecture, library source hash and a workload key.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import statistics
+from pathlib import Path
+
+DEFAULT = dict(waves_per_cu=0, fetch_min=16, traverse_min=1, grid_min=16, traverse_steps=2)
+SPACE = dict(
+    waves_per_cu=[0, 4, 8],
+    fetch_min=[4, 8, 16, 24, 32, 48],
+    traverse_min=[1, 2, 8],
+    grid_min=[4, 8, 16, 24, 32],
+    traverse_steps=[1, 2, 3, 4, 8],
+)
+
+
+def _cache_path() -> Path:
+    return Path(os.environ.get("CCS_AUTOTUNE_CACHE", Path.home() / ".cache" / "ccs_autotune.json"))
+
+
+def library_hash() -> str:
+    here = Path(__file__).resolve().parent / "csrc"
+    h = hashlib.sha256()
+    for p in sorted(here.glob("*")):
+        if p.suffix in (".hip", ".h", ".cpp"):
+            h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def workload_key(scene, batches) -> str:
+    """Scene size and depth, batch frames and sizes, and a hash of a few rays."""
+    import torch
+    info = scene.info()
+    h = hashlib.sha256()
+    h.update(repr((info["n_patches"], info["leaf_depth"], info["n_frames"])).encode())
+    for f, rays, _ in batches:
+        h.update(repr((int(f), int(rays.shape[0]))).encode())
+        if rays.shape[0]:
+            idx = torch.linspace(0, rays.shape[0] - 1, 16, device=rays.device).long()
+            h.update(rays[idx].cpu().numpy().tobytes())
+    return h.hexdigest()[:16]
+
+
+def time_launch(scene, batches, reps: int = 3) -> float:
+    """Median milliseconds of one batched launch of ``batches``."""
+    import torch
+    scene.intersect_batched(batches)  # warm-up
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        scene.intersect_batched(batches)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return statistics.median(ts)
+
+
+def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None) -> tuple[dict, float, list]:
+    """Coordinate descent over ``space`` from DEFAULT.  Returns (params, ms, trials)."""
+    space = space or SPACE
+    best = dict(DEFAULT)
+    trials = []
+    seen = {}
+
+    def run(p):
+        key = tuple(sorted(p.items()))
+        if key not in seen:
+            scene.set_launch(**p)
+            seen[key] = time_launch(scene, batches, reps)
+            trials.append((dict(p), seen[key]))
+            if log:
+                log(f"autotune {p} -> {seen[key]:.3f} ms")
+        return seen[key]
+
+    best_ms = run(best)
+    for _ in range(sweeps):
+        improved = False
+        for name, values in space.items():
+            for v in values:
+                cand = dict(best, **{name: v})
+                ms = run(cand)
+                if ms < best_ms * 0.995:
+                    best, best_ms, improved = cand, ms, True
+        if not improved:
+            break
+    scene.set_launch(**best)
+    return best, best_ms, trials
+
+
+def tuned(scene, batches, name: str = "", reps: int = 3, log=None, retune: bool = False) -> dict:
+    """Launch parameters for this (arch, library, workload): from the cache, else
+    tuned now and stored.  The scene is left configured with them."""
+    import torch
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+    key = f"{arch}|{library_hash()}|{name}|{workload_key(scene, batches)}"
+    path = _cache_path()
+    cache = {}
+    if path.exists():
+        try:
+            cache = json.loads(path.read_text())
+        except (OSError, json.JSONDecodeError):
+            cache = {}
+    if key in cache and not retune:
+        p = cache[key]["params"]
+        scene.set_launch(**p)
+        if log:
+            log(f"autotune cache hit {p}")
+        return p
+    p, ms, trials = tune(scene, batches, reps=reps, log=log)
+    cache[key] = {"params": p, "ms": ms, "trials": len(trials)}
+    try:
+        path.parent.mkdir(parents=True, exist_ok=True)
+        tmp = path.with_suffix(".tmp")
+        tmp.write_text(json.dumps(cache, indent=1, sort_keys=True))
+        tmp.replace(path)
+    except OSError:
+        pass
+    return p

@@ -114,3 +114,23 @@ def test_graph_captured_frame_loop_replays(anim, scene):
         torch.cuda.synchronize()
         for e, h in zip(eager, hits):
             assert np.array_equal(e.view(np.uint32), h.cpu().numpy().view(np.uint32))
+
+
+def test_autotuner_picks_a_setting_and_caches_it(anim, scene, tmp_path, monkeypatch):
+    from paper_1811_03510_amd import autotune
+    monkeypatch.setenv("CCS_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    rays = [torch.from_numpy(r).cuda() for r in anim.rays]
+    batches = [(f, r, None) for f, r in enumerate(rays)]
+    ref = [h.cpu().numpy() for h in scene.intersect_batched(batches)]
+    small = dict(waves_per_cu=[0, 4], fetch_min=[8, 16], traverse_min=[1], grid_min=[16], traverse_steps=[1, 2])
+    monkeypatch.setattr(autotune, "SPACE", small)
+    p = autotune.tuned(scene, batches, name="anim-test", reps=1, log=_say)
+    assert scene.get_launch() == p
+    assert (tmp_path / "tune.json").exists()
+    scene.set_launch()  # defaults
+    q = autotune.tuned(scene, batches, name="anim-test", reps=1, log=_say)  # from the cache
+    assert q == p and scene.get_launch() == p
+    got = [h.cpu().numpy() for h in scene.intersect_batched(batches)]
+    scene.set_launch()
+    for a, b in zip(ref, got):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
