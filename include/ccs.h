@@ -181,10 +181,11 @@ typedef struct ccs_launch_params {
   uint32_t traverse_min;   /* 1..64 lanes waiting to traverse to their next candidate */
   uint32_t grid_min;       /* 1..64 lanes waiting for a grid recomputation */
   uint32_t traverse_steps; /* BVH nodes a lane visits per traversal phase; 0 = until it reaches a candidate */
+  uint32_t decide_min;     /* 1..64 lanes waiting for the child-ordering network (learned order only) */
 } ccs_launch_params;
 
 /* Sets the launch configuration used by later ccs_intersect* calls on the
- * scene.  Defaults: {0, 16, 1, 16, 2}.  CCS_ERR_INVALID_ARG for thresholds
+ * scene.  Defaults: {0, 16, 1, 16, 2, 8}.  CCS_ERR_INVALID_ARG for thresholds
  * outside [1, 64].  Not synchronized with calls in flight on other threads. */
 ccs_status ccs_scene_set_launch(ccs_scene* scene, const ccs_launch_params* params);
 
@@ -201,6 +202,76 @@ ccs_status ccs_scene_get_launch(const ccs_scene* scene, ccs_launch_params* param
  * of n elements; out_rays may not alias rays.  Asynchronous on `stream`. */
 ccs_status ccs_bounce(const ccs_scene* scene, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                       uint32_t n, ccs_ray* out_rays, void* stream);
+
+/* ---------------------------------------------------- learned child ordering
+ * Alg. 3 visits the two halves of a split closest box first (Sec. 3.3).  A
+ * small network can choose instead at the splits along u where both halves are
+ * hit: it ranks the node's four grandchildren (u-half, v-half) from 16 inputs
+ * and the traversal enters the u-half, then one split later the v-half, of the
+ * top-ranked one (the v-choice only where both v-halves are hit and the children
+ * are not leaves).  Only hit halves are entered and every pending half is still
+ * visited, so hits are those of Alg. 3 up to the order in which equal or
+ * non-nested Gregory boxes are met.
+ *
+ * Inputs of a decision node (all scaled by s, the largest magnitude among the
+ * first 12): 0..11 its grid's corner points (u0,v0), (u1,v0), (u0,v1), (u1,v1)
+ * minus the ray's entry point into the node box, in the frame (e1, e2, d/|d|)
+ * of Duff et al. 2017; 12, 13 entry and exit distance of the lower minus the
+ * upper u-half times |d| / s, clamped to [-4, 4], / 4; 14 depth / 2L; 15 1 for a
+ * Gregory patch.  Network: 16 -> 32 -> 32 -> 4 with ReLU, parameters
+ * CCS_POLICY_PARAMS fp32 values in the order W1 (32 x 16, row = output unit),
+ * b1 (32), W2 (32 x 32), b2 (32), W3 (4 x 32), b3 (4); logit k ranks grandchild
+ * 2 * u_upper + v_upper.  Inference rounds inputs, weights and hidden
+ * activations to bfloat16 (nearest, ties to even) and accumulates in fp32 on the
+ * matrix cores. */
+#define CCS_POLICY_PARAMS 1732
+#define CCS_NO_LABEL 255
+
+/* Attaches the network (params: device pointer, CCS_POLICY_PARAMS fp32) to the
+ * scene: later ccs_intersect* calls use the learned order.  NULL detaches it
+ * (closest-first order).  The weights are packed on `stream`; params may be
+ * freed once the stream has passed the call.  CCS_ERR_UNSUPPORTED when the
+ * scene's BVH is deeper than 37 levels (the learned kernel's node stack). */
+ccs_status ccs_scene_set_policy(ccs_scene* scene, const float* params, void* stream);
+
+/* Training records for n rays and their hits on frame 0 (device pointers).
+ * Record r*L + k (L = leaf depth, k < L) describes the node of depth 2k on the
+ * path to ray r's reported leaf: features[16 (r L + k) ..] its 16 inputs and
+ * labels[r L + k] the grandchild holding the leaf; CCS_NO_LABEL (inputs zero)
+ * where the ray missed or does not meet both u-halves' boxes (slab test without
+ * the cap: the reported hit lies on the boxes' boundary as often as not).  features: n L 16 floats, labels:
+ * n L bytes, caller-owned.  Asynchronous on `stream`. */
+ccs_status ccs_policy_record(const ccs_scene* scene, const ccs_ray* rays, const ccs_hit* hits, uint32_t n,
+                             float* features, uint8_t* labels, void* stream);
+
+/* Logits (n x 4 fp32) of the network for n input rows (n x 16 fp32), computed
+ * as during traversal.  Device pointers.  Synchronous (returns when done). */
+ccs_status ccs_policy_infer(const float* params, const float* features, uint32_t n, float* logits, void* stream);
+
+/* Mean softmax cross-entropy over the rows whose label is not CCS_NO_LABEL and
+ * its gradient (CCS_POLICY_PARAMS fp32) with respect to params.  bf16 != 0:
+ * inputs, weights and hidden activations rounded to bfloat16 as in inference,
+ * the gradient passing straight through the roundings.  Device pointers; loss is
+ * one float.  Synchronous. */
+ccs_status ccs_policy_grad(const float* params, const float* features, const uint8_t* labels, uint32_t n,
+                           uint32_t bf16, float* grad, float* loss, void* stream);
+
+typedef struct ccs_train_params {
+  uint32_t steps;  /* optimizer steps */
+  uint32_t batch;  /* rows per step (at most n); an epoch is floor(n / batch) steps */
+  float lr, beta1, beta2, eps; /* Adam (Kingma & Ba 2015) */
+  uint64_t seed;   /* row order: a seeded affine permutation of the rows per epoch */
+  uint32_t bf16;   /* as in ccs_policy_grad */
+  uint32_t reserved;
+} ccs_train_params;
+
+/* Trains params (device, CCS_POLICY_PARAMS fp32, updated in place) with Adam
+ * on the rows (features n x 16, labels n) for tp->steps minibatches.
+ * loss_history: NULL or device array of tp->steps floats receiving each step's
+ * minibatch loss before its update.  Deterministic for a given seed.
+ * Synchronous. */
+ccs_status ccs_policy_train(float* params, const float* features, const uint8_t* labels, uint32_t n,
+                            const ccs_train_params* tp, float* loss_history, void* stream);
 
 ccs_status ccs_scene_info_get(const ccs_scene* scene, ccs_scene_info* info);
 

@@ -23,10 +23,13 @@ scale:
 
 where the node box is the union of the two u-half boxes of Alg. 3's split (box
 of the half's control points, grown by the parent's Gregory displacement on the
-max side), entries and exits are those of the slab test without the cap, and the
-node is used only when both halves pass the capped slab test.  The label of a
-node on the path to a ray's reported leaf is the grandchild holding that leaf,
-2 * (u-half) + (v-half).
+max side) and entries and exits are those of the slab test without the cap.
+During traversal the node is a decision when both halves pass the capped slab
+test.  A training record is the node of even depth on the path to a ray's
+reported leaf where the ray meets both halves' boxes (no cap: the reported hit
+lies on the boxes' boundary as often as not, where a capped test would turn on
+rounding); its label is the grandchild holding that leaf, 2 * (u-half) +
+(v-half).
 """
 from __future__ import annotations
 
@@ -91,10 +94,10 @@ def node_features(cp20, gregory: bool, ray8, u0, v0, size, depth: int, leaf_dept
     return f, True
 
 
-def path_records(cp20, gregory: bool, ray8, u: float, v: float, leaf_depth: int, cap: float):
+def path_records(cp20, gregory: bool, ray8, u: float, v: float, leaf_depth: int, cap: float = np.inf):
     """Records (features (L, 16), labels (L,)) along the path to the leaf holding
-    (u, v): one per even depth 0, 2, ..., 2L-2; label 255 where the node is not a
-    decision (not both u-halves hit)."""
+    (u, v): one per even depth 0, 2, ..., 2L-2; label 255 where the ray does not
+    meet both u-halves' boxes under `cap` (records use no cap)."""
     L = leaf_depth
     iu, iv = int(np.floor(u * 2 ** L)), int(np.floor(v * 2 ** L))
     feats, labels = np.zeros((L, 16)), np.full(L, NO_LABEL, dtype=np.uint8)

@@ -11,6 +11,8 @@ library defaults:
   traverse_min     lanes in BVH traversal that trigger a traversal phase
   grid_min         lanes waiting for a grid recompute that trigger that phase
   traverse_steps   BVH nodes a lane visits per traversal phase
+  decide_min       lanes waiting for the ordering network that trigger it
+                   (searched only when the scene has a learned order)
 
 timing the caller's workload (a list of batches for one ccs_intersect_batched
 call) with HIP events, median of a few repetitions.  The winner is cached in a
@@ -24,13 +26,14 @@ import os
 import statistics
 from pathlib import Path
 
-DEFAULT = dict(waves_per_cu=0, fetch_min=16, traverse_min=1, grid_min=16, traverse_steps=2)
+DEFAULT = dict(waves_per_cu=0, fetch_min=16, traverse_min=1, grid_min=16, traverse_steps=2, decide_min=8)
 SPACE = dict(
     waves_per_cu=[0, 4, 8],
     fetch_min=[4, 8, 16, 24, 32, 48],
     traverse_min=[1, 2, 8],
     grid_min=[4, 8, 16, 24, 32],
     traverse_steps=[1, 2, 3, 4, 8],
+    decide_min=[1, 4, 8, 16, 32],
 )
 
 
@@ -76,9 +79,12 @@ def time_launch(scene, batches, reps: int = 3) -> float:
     return statistics.median(ts)
 
 
-def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None) -> tuple[dict, float, list]:
+def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None,
+         learned: bool = False) -> tuple[dict, float, list]:
     """Coordinate descent over ``space`` from DEFAULT.  Returns (params, ms, trials)."""
-    space = space or SPACE
+    space = dict(space or SPACE)
+    if not learned:
+        space.pop("decide_min", None)
     best = dict(DEFAULT)
     trials = []
     seen = {}
@@ -108,12 +114,13 @@ def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None) -
     return best, best_ms, trials
 
 
-def tuned(scene, batches, name: str = "", reps: int = 3, log=None, retune: bool = False) -> dict:
+def tuned(scene, batches, name: str = "", reps: int = 3, log=None, retune: bool = False,
+          learned: bool = False) -> dict:
     """Launch parameters for this (arch, library, workload): from the cache, else
     tuned now and stored.  The scene is left configured with them."""
     import torch
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
-    key = f"{arch}|{library_hash()}|{name}|{workload_key(scene, batches)}"
+    key = f"{arch}|{library_hash()}|{name}|{'learned' if learned else 'plain'}|{workload_key(scene, batches)}"
     path = _cache_path()
     cache = {}
     if path.exists():
@@ -127,7 +134,7 @@ def tuned(scene, batches, name: str = "", reps: int = 3, log=None, retune: bool 
         if log:
             log(f"autotune cache hit {p}")
         return p
-    p, ms, trials = tune(scene, batches, reps=reps, log=log)
+    p, ms, trials = tune(scene, batches, reps=reps, log=log, learned=learned)
     cache[key] = {"params": p, "ms": ms, "trials": len(trials)}
     try:
         path.parent.mkdir(parents=True, exist_ok=True)

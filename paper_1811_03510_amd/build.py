@@ -22,10 +22,10 @@ ARCH = "gfx950"
 # Packed fp32 arithmetic stays off: the library's correctness must not depend on it.
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
-PER_FILE = {
-    "trace.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans", "-fgpu-flush-denormals-to-zero", "-fno-signed-zeros",
-                  "-ffp-contract=off"],
-}
+TRACE_FLAGS = ["-mno-amdgpu-ieee", "-fno-honor-nans", "-fgpu-flush-denormals-to-zero", "-fno-signed-zeros",
+               "-ffp-contract=off"]
+# policy.hip forms the learned order's inputs exactly as the intersection kernel does
+PER_FILE = {"trace.hip": TRACE_FLAGS, "policy.hip": TRACE_FLAGS}
 
 
 def sources():

@@ -23,8 +23,11 @@ COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "
 
 EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_counted", "ccs_bounce",
            "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
-           "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched")
+           "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched",
+           "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train")
 MAX_BATCHES = 32
+POLICY_PARAMS = 1732
+NO_LABEL = 255
 
 
 class CcsError(RuntimeError):
@@ -51,7 +54,13 @@ class Batch(C.Structure):
 
 class LaunchParams(C.Structure):
     _fields_ = [("waves_per_cu", C.c_uint32), ("fetch_min", C.c_uint32), ("traverse_min", C.c_uint32),
-                ("grid_min", C.c_uint32), ("traverse_steps", C.c_uint32)]
+                ("grid_min", C.c_uint32), ("traverse_steps", C.c_uint32), ("decide_min", C.c_uint32)]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("steps", C.c_uint32), ("batch", C.c_uint32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_uint64), ("bf16", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 _lib = None
@@ -80,6 +89,11 @@ def lib():
         L.ccs_refit_frame.argtypes = [vp, u32, vp, i32, vp]
         L.ccs_intersect_batched.argtypes = [vp, C.POINTER(Batch), u32, vp]
         L.ccs_scene_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
+        L.ccs_scene_set_policy.argtypes = [vp, vp, vp]
+        L.ccs_policy_record.argtypes = [vp, vp, vp, u32, vp, vp, vp]
+        L.ccs_policy_infer.argtypes = [vp, vp, u32, vp, vp]
+        L.ccs_policy_grad.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
+        L.ccs_policy_train.argtypes = [vp, vp, vp, u32, C.POINTER(TrainParams), vp, vp]
         for name in EXPORTS:
             if name not in ("ccs_scene_destroy", "ccs_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -180,15 +194,38 @@ class Scene:
         return out
 
     def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 1, grid_min: int = 16,
-                   traverse_steps: int = 2):
-        p = LaunchParams(waves_per_cu, fetch_min, traverse_min, grid_min, traverse_steps)
+                   traverse_steps: int = 2, decide_min: int = 8):
+        p = LaunchParams(waves_per_cu, fetch_min, traverse_min, grid_min, traverse_steps, decide_min)
         _check(lib().ccs_scene_set_launch(self._h, C.byref(p)))
 
     def get_launch(self) -> dict:
         p = LaunchParams()
         _check(lib().ccs_scene_get_launch(self._h, C.byref(p)))
         return dict(waves_per_cu=p.waves_per_cu, fetch_min=p.fetch_min, traverse_min=p.traverse_min,
-                    grid_min=p.grid_min, traverse_steps=p.traverse_steps)
+                    grid_min=p.grid_min, traverse_steps=p.traverse_steps, decide_min=p.decide_min)
+
+    def set_policy(self, params=None, stream=None):
+        """Learned child order with the network `params` (CUDA float32, 1732 values);
+        None returns to the closest-first order."""
+        if params is None:
+            _check(lib().ccs_scene_set_policy(self._h, None, _stream(stream)))
+            return
+        p = _params(params)
+        self._policy_keep = p
+        _check(lib().ccs_scene_set_policy(self._h, _ptr(p), _stream(stream)))
+
+    def record(self, rays, hits, stream=None):
+        """Training records of the ordering network: (features (N*L, 16), labels (N*L,) uint8)."""
+        import torch
+        r = self._rays(rays)
+        h = torch.as_tensor(hits)
+        if not h.is_cuda or h.dtype != torch.float32 or tuple(h.shape) != (r.shape[0], 4) or not h.is_contiguous():
+            raise ValueError("hits must be a contiguous (N, 4) float32 CUDA tensor")
+        L = self.info()["leaf_depth"]
+        f = torch.empty((r.shape[0] * L, 16), dtype=torch.float32, device=r.device)
+        y = torch.empty((r.shape[0] * L,), dtype=torch.uint8, device=r.device)
+        _check(lib().ccs_policy_record(self._h, _ptr(r), _ptr(h), r.shape[0], _ptr(f), _ptr(y), _stream(stream)))
+        return f, y
 
     @staticmethod
     def _rays(rays):
@@ -235,6 +272,59 @@ class Scene:
         _check(lib().ccs_bounce(self._h, _ptr(r), _ptr(hits.contiguous()), _ptr(uniforms.contiguous()), n,
                                 _ptr(out), _stream(stream)))
         return out
+
+
+def _params(params):
+    import torch
+    p = torch.as_tensor(params)
+    if not p.is_cuda or p.dtype != torch.float32 or p.numel() != POLICY_PARAMS or not p.is_contiguous():
+        raise ValueError(f"policy parameters must be a contiguous CUDA float32 tensor of {POLICY_PARAMS} values")
+    return p
+
+
+def _rows(x, width, dtype):
+    import torch
+    t = torch.as_tensor(x)
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or (width and (t.dim() != 2 or t.shape[1] != width)):
+        raise ValueError(f"expected a contiguous CUDA {dtype} tensor" + (f" of shape (N, {width})" if width else ""))
+    return t
+
+
+def policy_infer(params, features, stream=None):
+    """Logits (N, 4) of the ordering network, computed as during traversal."""
+    import torch
+    p, f = _params(params), _rows(features, 16, torch.float32)
+    z = torch.empty((f.shape[0], 4), dtype=torch.float32, device=f.device)
+    _check(lib().ccs_policy_infer(_ptr(p), _ptr(f), f.shape[0], _ptr(z), _stream(stream)))
+    return z
+
+
+def policy_grad(params, features, labels, bf16: bool = False, stream=None):
+    """(mean loss, gradient (1732,)) of the ordering network on labelled rows."""
+    import torch
+    p, f = _params(params), _rows(features, 16, torch.float32)
+    y = _rows(labels, 0, torch.uint8)
+    if y.numel() != f.shape[0]:
+        raise ValueError("one label per row")
+    g = torch.empty(POLICY_PARAMS, dtype=torch.float32, device=f.device)
+    loss = torch.empty(1, dtype=torch.float32, device=f.device)
+    _check(lib().ccs_policy_grad(_ptr(p), _ptr(f), _ptr(y), f.shape[0], int(bf16), _ptr(g), _ptr(loss),
+                                 _stream(stream)))
+    return float(loss.item()), g
+
+
+def policy_train(params, features, labels, steps: int, batch: int = 4096, lr: float = 3e-3, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, seed: int = 0, bf16: bool = True, stream=None):
+    """Adam on the ordering network, params updated in place; returns the per-step loss."""
+    import torch
+    p, f = _params(params), _rows(features, 16, torch.float32)
+    y = _rows(labels, 0, torch.uint8)
+    if y.numel() != f.shape[0]:
+        raise ValueError("one label per row")
+    hist = torch.empty(max(1, steps), dtype=torch.float32, device=f.device)
+    tp = TrainParams(steps, batch, lr, beta1, beta2, eps, seed, int(bf16), 0)
+    _check(lib().ccs_policy_train(_ptr(p), _ptr(f), _ptr(y), f.shape[0], C.byref(tp), _ptr(hist), _stream(stream)))
+    return hist[:steps]
 
 
 def hit_ids(hits) -> np.ndarray:

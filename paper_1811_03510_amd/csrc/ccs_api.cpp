@@ -2,6 +2,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -28,7 +29,7 @@ ccs_status hip_fail(hipError_t e, const char* what) {
   return fail(CCS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr int kTraversalStack = 48;  // matches the LDS stack of the intersect kernel
+constexpr int kTraversalStack = (int)ccs::kMaxBvhDepth;  // the LDS node stack of the intersect kernel
 constexpr uint32_t kQueueSlots = 256;  // ray-queue counters, one per launch in flight on a scene
 
 }  // namespace
@@ -43,7 +44,9 @@ struct ccs_scene {
   float* cp_stage = nullptr;  // device staging buffer for host refit input
   uint32_t* queues = nullptr;  // kQueueSlots ray-queue counters
   std::atomic<uint32_t> next_queue{0};
-  ccs_launch_params launch{0, 16, 1, 16, 2};
+  ccs_launch_params launch{0, 16, 1, 16, 2, 8};
+  uint2* policy_w = nullptr;   // packed network fragments, allocated on first use
+  float4* policy_b = nullptr;
   std::vector<void*> allocations;
 };
 
@@ -108,6 +111,60 @@ ccs_status check_finite(const float* cp, size_t count) {
   for (size_t k = 0; k < count; ++k)
     if (!std::isfinite(cp[k])) return fail(CCS_ERR_INVALID_ARG, "control point value " + std::to_string(k) + " is not finite");
   return CCS_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Device scratch owned by one synchronous call, freed on every return path.
+struct Scratch {
+  std::vector<void*> p;
+  ~Scratch() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  template <class T>
+  ccs_status alloc(T** out, size_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      *out = nullptr;
+      return fail(CCS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    p.push_back(q);
+    *out = static_cast<T*>(q);
+    return CCS_OK;
+  }
+};
+
+uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Row order of epoch e: index = (a * position + c) mod n with gcd(a, n) = 1.
+void epoch_permutation(uint64_t seed, uint64_t e, uint32_t n, uint64_t& a, uint64_t& c) {
+  uint64_t x = seed ^ (e * 0xD1B54A32D192ED03ull);
+  if (n <= 1) {
+    a = 1;
+    c = 0;
+    return;
+  }
+  a = splitmix64(x) % n;
+  if (a == 0) a = 1;
+  while (gcd64(a, n) != 1) a = a + 1 < n ? a + 1 : 1;
+  c = splitmix64(x) % n;
 }
 
 }  // namespace
@@ -346,7 +403,8 @@ static ccs_status launch_batches(const ccs_scene* s, const ccs::BatchTable& bt, 
   ccs_scene* m = const_cast<ccs_scene*>(s);
   const uint32_t slot = m->next_queue.fetch_add(1) % kQueueSlots;
   const uint32_t steps = s->launch.traverse_steps ? s->launch.traverse_steps : 0xFFFFFFFFu;
-  ccs::LaunchParams lp{s->launch.fetch_min, s->launch.traverse_min, s->launch.grid_min, steps, s->queues + slot};
+  ccs::LaunchParams lp{s->launch.fetch_min, s->launch.traverse_min, s->launch.grid_min, steps, s->launch.decide_min,
+                       s->queues + slot};
   hipError_t e = ccs::launch_intersect(s->dev, bt, counters, lp, s->launch.waves_per_cu, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "intersect launch");
   return CCS_OK;
@@ -410,7 +468,7 @@ ccs_status ccs_scene_set_launch(ccs_scene* s, const ccs_launch_params* p) {
   g_error.clear();
   if (!s || !p) return fail(CCS_ERR_INVALID_ARG, "scene or params is NULL");
   if (p->fetch_min < 1 || p->fetch_min > 64 || p->traverse_min < 1 || p->traverse_min > 64 || p->grid_min < 1 ||
-      p->grid_min > 64)
+      p->grid_min > 64 || p->decide_min < 1 || p->decide_min > 64)
     return fail(CCS_ERR_INVALID_ARG, "phase thresholds must be in [1, 64]");
   s->launch = *p;
   return CCS_OK;
@@ -420,7 +478,7 @@ ccs_status ccs_scene_get_launch(const ccs_scene* s, ccs_launch_params* p) {
   g_error.clear();
   if (!s || !p) return fail(CCS_ERR_INVALID_ARG, "scene or params is NULL");
   *p = s->launch;
-  if (p->waves_per_cu == 0) p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false);
+  if (p->waves_per_cu == 0) p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false, s->dev.policy.w != nullptr);
   return CCS_OK;
 }
 
@@ -433,6 +491,128 @@ ccs_status ccs_bounce(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hi
   if ((const void*)out_rays == (const void*)rays) return fail(CCS_ERR_INVALID_ARG, "out_rays aliases rays");
   hipError_t e = ccs::launch_bounce(s->dev, rays, hits, uniforms, n, out_rays, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "bounce launch");
+  return CCS_OK;
+}
+
+// ------------------------------------------------------- learned child ordering
+ccs_status ccs_scene_set_policy(ccs_scene* s, const float* params, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (!params) {
+    s->dev.policy = ccs::PolicyDev{nullptr, nullptr};
+    return CCS_OK;
+  }
+  if (s->bvh_depth >= ccs::kMaxBvhDepthLearned)
+    return fail(CCS_ERR_UNSUPPORTED, "BVH depth " + std::to_string(s->bvh_depth) +
+                                         " exceeds the learned-order kernel's node stack");
+  if (!s->policy_w) {
+    ccs_status st = dev_alloc(s, &s->policy_w, (size_t)ccs::kPolicyWTiles * 64);
+    if (st == CCS_OK) st = dev_alloc(s, &s->policy_b, (size_t)ccs::kPolicyBTiles * 64);
+    if (st != CCS_OK) return st;
+  }
+  hipError_t e = ccs::launch_policy_pack(params, s->policy_w, s->policy_b, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "policy pack launch");
+  s->dev.policy = ccs::PolicyDev{s->policy_w, s->policy_b};
+  return CCS_OK;
+}
+
+ccs_status ccs_policy_record(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hits, uint32_t n,
+                             float* features, uint8_t* labels, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (n == 0) return CCS_OK;
+  if (!rays || !hits || !features || !labels) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if ((uint64_t)n * (uint64_t)s->dev.leaf_depth >= (1ull << 36))
+    return fail(CCS_ERR_INVALID_ARG, "too many records for one call");
+  hipError_t e = ccs::launch_record(s->dev, rays, hits, n, features, labels, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "record launch");
+  return CCS_OK;
+}
+
+ccs_status ccs_policy_infer(const float* params, const float* features, uint32_t n, float* logits, void* stream) {
+  g_error.clear();
+  if (n == 0) return CCS_OK;
+  if (!params || !features || !logits) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  Scratch sc;
+  uint2* w = nullptr;
+  float4* b = nullptr;
+  ccs_status st = sc.alloc(&w, (size_t)ccs::kPolicyWTiles * 64);
+  if (st == CCS_OK) st = sc.alloc(&b, (size_t)ccs::kPolicyBTiles * 64);
+  if (st != CCS_OK) return st;
+  hipStream_t str = (hipStream_t)stream;
+  hipError_t e = ccs::launch_policy_pack(params, w, b, str);
+  if (e == hipSuccess) e = ccs::launch_policy_infer(ccs::PolicyDev{w, b}, features, n, logits, str);
+  if (e == hipSuccess) e = hipStreamSynchronize(str);
+  if (e != hipSuccess) return hip_fail(e, "policy inference");
+  return CCS_OK;
+}
+
+ccs_status ccs_policy_grad(const float* params, const float* features, const uint8_t* labels, uint32_t n,
+                           uint32_t bf16, float* grad, float* loss, void* stream) {
+  g_error.clear();
+  if (!params || !grad || !loss || (n > 0 && (!features || !labels)))
+    return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  hipStream_t str = (hipStream_t)stream;
+  const uint32_t nblk = std::max<uint32_t>(1, (n + 63) / 64);
+  Scratch sc;
+  float *partial = nullptr, *lossp = nullptr;
+  ccs_status st = sc.alloc(&partial, (size_t)nblk * ccs::kPolicyParams);
+  if (st == CCS_OK) st = sc.alloc(&lossp, (size_t)2 * nblk);
+  if (st != CCS_OK) return st;
+  hipError_t e = hipSuccess;
+  if (n == 0) {
+    e = ccs::launch_fill(partial, ccs::kPolicyParams, 0.0f, str);
+    if (e == hipSuccess) e = ccs::launch_fill(lossp, 2, 0.0f, str);
+  } else {
+    e = ccs::launch_mlp_grad(params, features, labels, n, n, 0, 1, 0, bf16 != 0, partial, lossp, str);
+  }
+  if (e == hipSuccess) e = ccs::launch_mlp_reduce(partial, lossp, nblk, grad, loss, str);
+  if (e == hipSuccess) e = hipStreamSynchronize(str);
+  if (e != hipSuccess) return hip_fail(e, "policy gradient");
+  return CCS_OK;
+}
+
+ccs_status ccs_policy_train(float* params, const float* features, const uint8_t* labels, uint32_t n,
+                            const ccs_train_params* tp, float* loss_history, void* stream) {
+  g_error.clear();
+  if (!params || !tp || (n > 0 && (!features || !labels))) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if (n == 0 || tp->steps == 0) return CCS_OK;
+  if (tp->batch == 0) return fail(CCS_ERR_INVALID_ARG, "batch is 0");
+  if (!(tp->lr > 0.0f) || !(tp->beta1 >= 0.0f && tp->beta1 < 1.0f) || !(tp->beta2 >= 0.0f && tp->beta2 < 1.0f) ||
+      !(tp->eps > 0.0f))
+    return fail(CCS_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+  const uint32_t batch = std::min(tp->batch, n);
+  const uint32_t nblk = (batch + 63) / 64;
+  const uint32_t per_epoch = std::max<uint32_t>(1, n / batch);
+  hipStream_t str = (hipStream_t)stream;
+  Scratch sc;
+  float *partial = nullptr, *lossp = nullptr, *m = nullptr, *v = nullptr;
+  ccs_status st = sc.alloc(&partial, (size_t)nblk * ccs::kPolicyParams);
+  if (st == CCS_OK) st = sc.alloc(&lossp, (size_t)2 * nblk);
+  if (st == CCS_OK) st = sc.alloc(&m, (size_t)ccs::kPolicyParams);
+  if (st == CCS_OK) st = sc.alloc(&v, (size_t)ccs::kPolicyParams);
+  if (st != CCS_OK) return st;
+  hipError_t e = ccs::launch_fill(m, ccs::kPolicyParams, 0.0f, str);
+  if (e == hipSuccess) e = ccs::launch_fill(v, ccs::kPolicyParams, 0.0f, str);
+  double b1t = 1.0, b2t = 1.0;
+  uint64_t pa = 1, pc = 0, cur_epoch = ~0ull;
+  for (uint32_t step = 0; step < tp->steps && e == hipSuccess; ++step) {
+    const uint64_t epoch = step / per_epoch;
+    if (epoch != cur_epoch) {
+      epoch_permutation(tp->seed, epoch, n, pa, pc);
+      cur_epoch = epoch;
+    }
+    const uint64_t pos0 = (uint64_t)(step % per_epoch) * batch;
+    e = ccs::launch_mlp_grad(params, features, labels, n, batch, pos0, pa, pc, tp->bf16 != 0, partial, lossp, str);
+    b1t *= tp->beta1;
+    b2t *= tp->beta2;
+    if (e == hipSuccess)
+      e = ccs::launch_mlp_adam(params, m, v, partial, lossp, nblk, tp->lr, tp->beta1, tp->beta2, tp->eps,
+                               (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)),
+                               loss_history ? loss_history + step : nullptr, str);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(str);
+  if (e != hipSuccess) return hip_fail(e, "policy training");
   return CCS_OK;
 }
 

@@ -8,6 +8,14 @@
 
 namespace ccs {
 
+// Child-ordering network as matrix-core operand fragments (layout in policy.h).
+constexpr int kPolicyParams = 1732;
+constexpr int kPolicyWTiles = 8, kPolicyBTiles = 5;
+struct PolicyDev {
+  const uint2* w;   // kPolicyWTiles * 64 lanes x 4 bfloat16
+  const float4* b;  // kPolicyBTiles * 64 lanes x 4 fp32
+};
+
 // BVH node: 64 bytes = 4 float4.
 //   f[0] = (lo0.x, lo0.y, lo0.z, hi0.x)
 //   f[1] = (hi0.y, hi0.z, lo1.x, lo1.y)
@@ -29,6 +37,7 @@ struct DeviceScene {
   uint32_t n_frames;         // frames: copies of recs and node boxes sharing one topology
   size_t frame_rec_floats;   // floats per frame in recs (n_patches * kRecFloats)
   size_t frame_node_f4;      // float4s per frame in nodes (n_nodes * 4)
+  PolicyDev policy;          // set: learned child ordering (see policy.h); w == nullptr: closest first
 };
 
 // Rays of one launch: up to kMaxBatches batches, each with its own frame, ray
@@ -46,14 +55,32 @@ struct BatchTable {
 // Phase thresholds of the persistent intersection kernel (see trace.hip) and
 // the launch's ray-queue counter.
 struct LaunchParams {
-  uint32_t fetch_min, traverse_min, grid_min, traverse_steps;
+  uint32_t fetch_min, traverse_min, grid_min, traverse_steps, decide_min;
   uint32_t* queue;
 };
 
-int max_waves_per_cu(bool counted);
+// BVH depth the learned variant's node stack holds (its LDS also holds the
+// policy's inputs); the closest-first variant holds kMaxBvhDepth.
+constexpr uint32_t kMaxBvhDepth = 48;
+constexpr uint32_t kMaxBvhDepthLearned = 38;
+
+int max_waves_per_cu(bool counted, bool learned);
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
                             uint32_t waves_per_cu, hipStream_t stream);
 hipError_t launch_refit(const DeviceScene& s, const float* cp_world, hipStream_t stream);
+hipError_t launch_policy_pack(const float* params, uint2* w, float4* b, hipStream_t stream);
+hipError_t launch_policy_infer(const PolicyDev& P, const float* x, uint32_t n, float* z, hipStream_t stream);
+hipError_t launch_record(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, uint32_t n, float* feats,
+                         uint8_t* labels, hipStream_t stream);
+hipError_t launch_mlp_grad(const float* theta, const float* X, const uint8_t* Y, uint32_t n, uint32_t batch,
+                           uint64_t pos0, uint64_t pa, uint64_t pc, int bf16, float* partial, float* lossp,
+                           hipStream_t stream);
+hipError_t launch_mlp_reduce(const float* partial, const float* lossp, uint32_t nblk, float* grad, float* loss,
+                             hipStream_t stream);
+hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* partial, const float* lossp, uint32_t nblk,
+                           float lr, float beta1, float beta2, float eps, float c1, float c2, float* loss,
+                           hipStream_t stream);
+hipError_t launch_fill(float* p, uint32_t n, float value, hipStream_t stream);
 hipError_t launch_bounce(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                          uint32_t n, ccs_ray* out, hipStream_t stream);
 

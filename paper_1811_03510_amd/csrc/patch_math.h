@@ -113,6 +113,29 @@ struct RayP {  // a ray in some frame: origin, reciprocal direction, tmin
 // -o/d would carry an error relative to |o|/|d|, not to the distance).
 constexpr float kFarScale = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);
 
+__device__ __forceinline__ float safe_inv(float d) {
+  // a zero component gets a huge finite reciprocal: the slab of that axis is then
+  // unbounded for origins between the planes and empty otherwise, without 0*inf
+  return d == 0.0f ? copysignf(1e30f, d) : __frcp_rn(d);
+}
+
+// Patch frame of a ray: anchored at the patch's anchor, origin moved along the
+// ray to (about) the point closest to the anchor, computed in double and rounded
+// once.  Distances inside the patch are then of the patch's size, so their
+// rounding, and the conservative widening of the slab test that covers it, are
+// relative to the patch rather than to the distance from the ray origin (Sec.
+// 3.4: anchoring for precision).  Any t0 gives the same ray; patch-frame
+// distances are world distances minus t0.
+__device__ __forceinline__ void patch_frame(float4 anchor, float ox, float oy, float oz, float dx, float dy, float dz,
+                                            float tmin, float& pox, float& poy, float& poz, float& ptmin, float& t0) {
+  const float qx = anchor.x - ox, qy = anchor.y - oy, qz = anchor.z - oz;
+  t0 = (qx * dx + qy * dy + qz * dz) * __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
+  pox = (float)fma((double)t0, (double)dx, (double)ox - (double)anchor.x);
+  poy = (float)fma((double)t0, (double)dy, (double)oy - (double)anchor.y);
+  poz = (float)fma((double)t0, (double)dz, (double)oz - (double)anchor.z);
+  ptmin = (float)((double)tmin - (double)t0);
+}
+
 // Closed slab test on [tmin, cap]; returns the entry distance or +inf when missed.
 __device__ __forceinline__ float slab(const RayP& r, float lx, float ly, float lz, float hx, float hy, float hz,
                                       float cap) {

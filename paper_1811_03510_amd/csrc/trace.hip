@@ -34,13 +34,13 @@
 
 #include "ccs_internal.h"
 #include "patch_math.h"
+#include "policy.h"
 
 namespace ccs {
 
 constexpr int kBlock = 64;
-constexpr int kStack = 48;
 
-enum Mode : int { kFetch = 0, kTraverse = 1, kStep = 2, kGrid = 3, kDead = 4 };
+enum Mode : int { kFetch = 0, kTraverse = 1, kStep = 2, kGrid = 3, kDead = 4, kDecide = 5 };
 
 struct Counts {
   uint32_t node, cand, split, backtrack, greg, leaf, crop, cand_greg;
@@ -48,12 +48,6 @@ struct Counts {
 
 __device__ __forceinline__ bool finite_bits(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
 __device__ __forceinline__ bool nan_bits(float x) { return (__float_as_uint(x) & 0x7FFFFFFFu) > 0x7F800000u; }
-
-__device__ __forceinline__ float safe_inv(float d) {
-  // a zero component gets a huge finite reciprocal: the slab of that axis is then
-  // unbounded for origins between the planes and empty otherwise, without 0*inf
-  return d == 0.0f ? copysignf(1e30f, d) : __frcp_rn(d);
-}
 
 // Batch of launch ray k (a wave-uniform scan: the table is never indexed per lane).
 __device__ __forceinline__ uint32_t batch_of(const BatchTable& bt, uint32_t k) {
@@ -86,10 +80,20 @@ __device__ __forceinline__ void write_hit(const BatchTable& bt, uint32_t* __rest
   }
 }
 
-template <bool kStats>
+// kLearned: the child-ordering network picks the u-half at decision nodes
+// (policy.h).  The lane first descends the closest-first way, stores the
+// node's policy inputs and waits in DECIDE; the wave then runs the network for
+// all waiting lanes on the matrix cores.  A lane whose network prefers the other
+// u-half flips that level's path bit (its trail bit stays set, so the
+// closest-first half becomes the pending sibling) and has its grid recomputed;
+// one split later it takes the v-half of the network's top grandchild when both
+// v-halves are hit.
+template <bool kStats, bool kLearned>
 __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
                                                   LaunchParams lp) {
+  constexpr int kStack = kLearned ? (int)kMaxBvhDepthLearned : (int)kMaxBvhDepth;
   __shared__ int stack[kStack * kBlock];
+  __shared__ __align__(16) uint32_t s_feat[kLearned ? 64 * 8 : 4];  // policy inputs, then logits, per lane
   __shared__ float s_dir[3][kBlock];  // world direction: read only when a candidate is set up
   __shared__ float s_uv[2][kBlock];   // (u, v) of the best hit: written only by leaf records
   const int lane = threadIdx.x;
@@ -113,6 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
   float dx = 0.0f, dy = 0.0f, dz = 0.0f;
   uint32_t code = 0, trail = 0, mirror = 0;
   int depth = 0;
+  uint32_t vpref = 0;  // learned order: bit 0 set = take the v-half in bit 1 at the next split
 
   for (;;) {
     if (__ballot(mode != kDead) == 0) break;
@@ -120,6 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
     uint64_t mt = __ballot(mode == kTraverse);
     uint64_t ms = __ballot(mode == kStep);
     uint64_t mg = __ballot(mode == kGrid);
+    if (kLearned) ms |= __ballot(mode == kDecide);  // lanes that will step once decided
 
     // ------------------------------------------------------------ fetch rays
     if (mf != 0 && ((uint32_t)__popcll(mf) >= lp.fetch_min || (mt | ms | mg) == 0)) {
@@ -185,19 +191,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
           const float* rec = recs + (size_t)rec_idx * kRecFloats;
           const float4 meta = reinterpret_cast<const float4*>(rec)[15];
           pmeta = __float_as_uint(meta.w);
-          // Patch frame: anchored at the patch's anchor, origin moved along the ray to
-          // (about) the point closest to the anchor, computed in double and rounded
-          // once.  Distances inside the patch are then of the patch's size, so their
-          // rounding, and the conservative widening of the slab test that covers it,
-          // are relative to the patch rather than to the distance from the ray
-          // origin (Sec. 3.4: anchoring for precision).  Any t0 gives the same ray.
-          const float wdx = s_dir[0][lane], wdy = s_dir[1][lane], wdz = s_dir[2][lane];
-          const float qx = meta.x - wr.ox, qy = meta.y - wr.oy, qz = meta.z - wr.oz;
-          pt0 = (qx * wdx + qy * wdy + qz * wdz) * __builtin_amdgcn_rcpf(wdx * wdx + wdy * wdy + wdz * wdz);
-          pox = (float)fma((double)pt0, (double)wdx, (double)wr.ox - (double)meta.x);
-          poy = (float)fma((double)pt0, (double)wdy, (double)wr.oy - (double)meta.y);
-          poz = (float)fma((double)pt0, (double)wdz, (double)wr.oz - (double)meta.z);
-          ptmin = (float)((double)wr.tmin - (double)pt0);
+          patch_frame(meta, wr.ox, wr.oy, wr.oz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane], wr.tmin, pox, poy,
+                      poz, ptmin, pt0);
           code = trail = mirror = 0;
           depth = 0;
           if (pmeta & kGregoryBit) {
@@ -240,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
         }
       }
       ms = __ballot(mode == kStep);
+      if (kLearned) ms |= __ballot(mode == kDecide);
       mg = __ballot(mode == kGrid);
     }
 
@@ -271,6 +267,26 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
       }
     }
 
+    // ----------------------------- learned order: the network for waiting lanes
+    if (kLearned) {
+      const uint64_t md = __ballot(mode == kDecide);
+      if (md != 0 && ((uint32_t)__popcll(md) >= lp.decide_min || __ballot(mode == kStep) == 0)) {
+        policy_wave(s.policy, s_feat, md, lane);  // the whole wave: matrix-core operands span all lanes
+        if (mode == kDecide) {
+          const float4 lg = reinterpret_cast<const float4*>(s_feat)[2 * lane];
+          const uint32_t top = policy_top(lg.x, lg.y, lg.z, lg.w);
+          const uint32_t bit = 1u << (L2 - depth);  // path bit of the u-split just taken
+          vpref = 1u | ((top & 1u) << 1);
+          if (((top >> 1) != 0) != ((code & bit) != 0)) {
+            code ^= bit;  // the other u-half first; the trail bit keeps the closest-first one pending
+            mode = kGrid;
+          } else {
+            mode = (pmeta & kGregoryBit) ? kGrid : kStep;
+          }
+        }
+      }
+    }
+
     // -------------------------------------------------- one subdivision step
     if (mode == kStep) {
       if (kStats) cnt.split++;
@@ -288,11 +304,29 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
       const bool mir = ((mirror >> axis) & 1u) != 0;
       const bool h_lo = mir ? hb : ha, h_up = mir ? ha : hb;
       const float t_lo = mir ? tb : ta, t_up = mir ? ta : tb;
-      const bool go_up = h_up && (!h_lo || t_up < t_lo);
+      bool go_up = h_up && (!h_lo || t_up < t_lo);
       const uint32_t bit = 1u << (L2 - 1 - depth);
+      const uint32_t mirror0 = mirror;
+      bool decide = false;
+      if (kLearned) {
+        // v-split after a decision: the network's v-half when both are hit (not at the
+        // leaf pair, which is resolved by distance)
+        if ((vpref & 1u) && axis == 1 && ha && hb && depth != L2 - 1) go_up = (vpref & 2u) != 0;
+        vpref = 0;
+        decide = axis == 0 && ha && hb;
+      }
       // the chosen half replaces the grid on every path: when the lane backtracks or
       // leaves the patch instead, the grid is rebuilt before it is read again
       const bool second = go_up != mir;
+      float ocx[2], ocy[2], ocz[2];  // learned order: the node's corners at the other storage end
+      if (kLearned && decide) {
+        ocx[0] = second ? ex[0].v[0] : ex[0].v[6];
+        ocx[1] = second ? ex[3].v[0] : ex[3].v[6];
+        ocy[0] = second ? ey[0].v[0] : ey[0].v[6];
+        ocy[1] = second ? ey[3].v[0] : ey[3].v[6];
+        ocz[0] = second ? ez[0].v[0] : ez[0].v[6];
+        ocz[1] = second ? ez[3].v[0] : ez[3].v[6];
+      }
       take_half(ex, second, G.x);
       take_half(ey, second, G.y);
       take_half(ez, second, G.z);
@@ -316,6 +350,28 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
           if (second) mirror ^= (1u << axis);
           depth++;
           if (pmeta & kGregoryBit) mode = kGrid;  // Alg. 3 recomputes a Gregory grid at every node
+          if (kLearned && decide) {
+            // the node's corners in storage order (0,0), (3,0), (0,3), (3,3): the taken
+            // end is now the first column of G
+            float sx[4], sy[4], sz[4];
+            sx[0] = second ? ocx[0] : G.x[0][0];
+            sx[1] = second ? G.x[0][0] : ocx[0];
+            sx[2] = second ? ocx[1] : G.x[3][0];
+            sx[3] = second ? G.x[3][0] : ocx[1];
+            sy[0] = second ? ocy[0] : G.y[0][0];
+            sy[1] = second ? G.y[0][0] : ocy[0];
+            sy[2] = second ? ocy[1] : G.y[3][0];
+            sy[3] = second ? G.y[3][0] : ocy[1];
+            sz[0] = second ? ocz[0] : G.z[0][0];
+            sz[1] = second ? G.z[0][0] : ocz[0];
+            sz[2] = second ? ocz[1] : G.z[3][0];
+            sz[3] = second ? G.z[3][0] : ocz[1];
+            float f[16];
+            policy_inputs(sx, sy, sz, mirror0, pox, poy, poz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane], sp2,
+                          depth - 1, s.leaf_depth, (pmeta & kGregoryBit) != 0, f);
+            policy_store_inputs(s_feat, lane, f);
+            mode = kDecide;
+          }
         }
       }
       if (backtrack) {
@@ -342,33 +398,44 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
 
 __global__ void k_queue_reset(uint32_t* q) { *q = 0u; }
 
-template <bool kStats>
+template <bool kStats, bool kLearned>
 static int resident_waves_per_cu() {
   static int per_cu = -1;
   if (per_cu < 0) {
     int v = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace<kStats>, kBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace<kStats, kLearned>, kBlock, 0);
     per_cu = std::max(1, v);
   }
   return per_cu;
 }
 
-int max_waves_per_cu(bool counted) { return counted ? resident_waves_per_cu<true>() : resident_waves_per_cu<false>(); }
+int max_waves_per_cu(bool counted, bool learned) {
+  if (learned) return counted ? resident_waves_per_cu<true, true>() : resident_waves_per_cu<false, true>();
+  return counted ? resident_waves_per_cu<true, false>() : resident_waves_per_cu<false, false>();
+}
 
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
                             uint32_t waves_per_cu, hipStream_t stream) {
   const uint32_t n = bt.prefix[bt.n_batches];
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, stream, lp.queue);
-  int per_cu = max_waves_per_cu(counters != nullptr);
+  const bool learned = s.policy.w != nullptr;
+  int per_cu = max_waves_per_cu(counters != nullptr, learned);
   if (waves_per_cu > 0) per_cu = std::min(per_cu, (int)waves_per_cu);
   const uint32_t waves = (uint32_t)(per_cu * s.n_cus);
   const uint32_t needed = (n + kBlock - 1) / kBlock;
   const dim3 grid(std::min(waves, needed)), block(kBlock);
-  if (counters)
-    hipLaunchKernelGGL(k_trace<true>, grid, block, 0, stream, s, bt, counters, lp);
-  else
-    hipLaunchKernelGGL(k_trace<false>, grid, block, 0, stream, s, bt, nullptr, lp);
+  if (learned) {
+    if (counters)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace<true, true>), grid, block, 0, stream, s, bt, counters, lp);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace<false, true>), grid, block, 0, stream, s, bt, nullptr, lp);
+  } else {
+    if (counters)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace<true, false>), grid, block, 0, stream, s, bt, counters, lp);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace<false, false>), grid, block, 0, stream, s, bt, nullptr, lp);
+  }
   return hipGetLastError();
 }
 
