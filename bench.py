@@ -98,11 +98,14 @@ def main():
     ap.add_argument("--no-counters", action="store_true", help="skip the counted launch (roofline)")
     ap.add_argument("--launch", default="",
                     help="waves_per_cu,fetch_min,traverse_min,grid_min,traverse_steps (default: library's)")
-    ap.add_argument("--only", choices=["", "plain", "batched"], default="",
+    ap.add_argument("--only", choices=["", "plain", "batched", "learned"], default="",
                     help="time one variant only (a profiler run then sees one launch shape)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batched variant with the given/default launch instead of the tuned one")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--policy-rays", type=int, default=1 << 20,
+                    help="secondary rays on the 512-patch torus whose records train the ordering network")
+    ap.add_argument("--policy-steps", type=int, default=4000, help="Adam steps of the ordering network")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer once (a plain copy kernel of known size that "
                          "scales the profiler's FETCH_SIZE / WRITE_SIZE)")
@@ -217,16 +220,58 @@ def main():
                 and np.array_equal(hits_d.view(np.uint32), hd.cpu().numpy().view(np.uint32)))
         log(f"batched: {ms:.3f} ms/step -> {variants['batched']['mrays_per_s']:.1f} MRays/s "
             f"(launch {variants['batched']['launch']})")
-    head = "batched" if "batched" in variants else "plain"
+    learned_hits = None
+    if args.only in ("", "learned"):
+        policy, pstats = train_policy(args, torch, ccs, scenes)
+        scene.set_policy(policy)
+        hlp, hld = torch.empty_like(hp), torch.empty_like(hd)
+        lbatches = [(0, prim, hlp), (0, diff, hld)]
+
+        def learned_step(evs=None):
+            if evs:
+                evs[0].record(stream)
+            scene.intersect_batched(lbatches)
+            if evs:
+                evs[1].record(stream)
+
+        if args.autotune:
+            from paper_1811_03510_amd import autotune
+            tuned = autotune.tuned(scene, lbatches, name=w.name, learned=True, log=log if args.verbose else None)
+            log(f"autotuned learned launch {tuned}")
+        laps, ms = timed(learned_step, 2)
+        learned_hits = (hlp.cpu().numpy(), hld.cpu().numpy())
+        v = {"ms_per_step": ms, "mrays_per_s": (n_p + n_d) / (ms * 1e-3) / 1e6, "launch": scene.get_launch(),
+             "launches_per_step": 1, "kernel_ms": float(np.mean(laps)), "autotuned": bool(args.autotune),
+             "ms_median": float(np.median(laps)), "policy": pstats}
+        if "batched" in variants:
+            v["identical_to_closest_first"] = {
+                "primary": float(np.mean(np.all(learned_hits[0].view(np.uint32) == hits_p.view(np.uint32), axis=1))),
+                "diffuse": float(np.mean(np.all(learned_hits[1].view(np.uint32) == hits_d.view(np.uint32), axis=1)))}
+        if not args.no_counters:
+            _, lc_p = scene.intersect_counted(prim)
+            _, lc_d = scene.intersect_counted(diff)
+            lc_p, lc_d = lc_p.cpu().numpy(), lc_d.cpu().numpy()
+            v["work_per_ray"] = {c: {"primary": float(lc_p[:, k].mean()), "diffuse": float(lc_d[:, k].mean())}
+                                 for k, c in enumerate(COUNTERS)}
+        scene.set_policy(None)
+        variants["learned_batched"] = v
+        log(f"learned batched: {ms:.3f} ms/step -> {v['mrays_per_s']:.1f} MRays/s; {pstats}")
+    head = "batched" if "batched" in variants else ("plain" if "plain" in variants else "learned_batched")
+    if "learned_batched" in variants and head != "learned_batched" and \
+            variants["learned_batched"]["mrays_per_s"] > variants[head]["mrays_per_s"]:
+        head = "learned_batched"  # kept only if it also passes the oracle gate below
     ms_step = variants[head]["ms_per_step"]
     value = variants[head]["mrays_per_s"]
 
     roofline = None
     work = None
     if not args.no_counters:
+        if head == "learned_batched":
+            scene.set_policy(policy)
         _, cp_ = scene.intersect_counted(prim)
         _, cd_ = scene.intersect_counted(diff)
         torch.cuda.synchronize()
+        scene.set_policy(None)
         cp_, cd_ = cp_.cpu().numpy(), cd_.cpu().numpy()
         ops_p, ops_d = algorithmic_ops(cp_), algorithmic_ops(cd_)
         per_launch = variants[head]["launches_per_step"]
@@ -236,7 +281,8 @@ def main():
         bytes_launch = traffic_from_profiles(launch_ms)
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
                     "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                    "traffic": bytes_launch, "kernel": "k_trace<false>",
+                    "traffic": bytes_launch if head != "learned_batched" else None,
+                    "kernel": "k_trace<false, true>" if head == "learned_batched" else "k_trace<false, false>",
                     "kernel_avg_ms": round(launch_ms, 4),
                     "ops_per_launch": ops_launch,
                     "ops_per_ray": {"primary": ops_p / n_p, "diffuse": ops_d / n_d}}
@@ -272,6 +318,15 @@ def main():
         rd = gate(hits_d[sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="diffuse")
         parity = {c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
                       "excused": r["excused"], "ok": r["ok"]} for c, r in (("primary", rp), ("diffuse", rd))}
+        if learned_hits is not None:
+            lp_ = gate(learned_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="l-primary")
+            ld_ = gate(learned_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="l-diffuse")
+            variants["learned_batched"]["parity_sample"] = {
+                c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
+                    "excused": r["excused"], "ok": r["ok"]} for c, r in (("primary", lp_), ("diffuse", ld_))}
+            if head == "learned_batched" and not (lp_["ok"] and ld_["ok"]):
+                head = "batched" if "batched" in variants else "plain"  # a failing variant reports nothing
+                ms_step, value = variants[head]["ms_per_step"], variants[head]["mrays_per_s"]
         log(f"cpu baseline: {cpu['value']} MRays/s on {threads} threads; parity {parity}")
 
     out = {
@@ -290,7 +345,9 @@ def main():
         "config": {"workload": (f"{w.name}: {w.cp.shape[0]} patches "
                                 f"({int(w.types.sum())} Gregory), {n_p} primary + {n_d} secondary rays per step"),
                    "variant": {"plain": "closest-first order, one launch per ray class",
-                               "batched": "closest-first order, both ray classes in one autotuned launch"}[head],
+                               "batched": "closest-first order, both ray classes in one autotuned launch",
+                               "learned_batched": "learned child order, both ray classes in one autotuned launch"
+                               }[head],
                    "launch": variants[head]["launch"],
                    "leaf_depth": w.leaf_depth},
         "variants": variants,
@@ -303,6 +360,41 @@ def main():
         "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)
+
+
+def train_policy(args, torch, ccs, scenes):
+    """Ordering network trained on records of secondary rays of the 512-patch torus
+    (GPU: record, Adam in bfloat16); returns (params on the GPU, statistics)."""
+    t0 = time.time()
+    c1 = scenes.config1()
+    rays = scenes.policy_training_rays(args.policy_rays)
+    gen_s = time.time() - t0
+    g1 = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+
+    def records(r_np):
+        r = torch.from_numpy(r_np).cuda()
+        f, y = g1.record(r, g1.intersect(r))
+        keep = (y != ccs.NO_LABEL).nonzero().squeeze(1)
+        return f[keep].contiguous(), y[keep].contiguous()
+
+    f, y = records(rays)
+    th = torch.from_numpy(scenes.mlp_init()).cuda()
+    torch.cuda.synchronize()
+    t1 = time.time()
+    hist = ccs.policy_train(th, f, y, steps=args.policy_steps, batch=8192, lr=3e-3, seed=1, bf16=True)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    fe, ye = records(c1.diffuse)  # held out: the torus workload's own secondary rays
+    z = ccs.policy_infer(th, fe).cpu().numpy()
+    ye, fe12 = ye.cpu().numpy(), fe[:, 12].cpu().numpy()
+    hist = hist.cpu().numpy()
+    return th, {"train_rays": len(rays), "records": int(f.shape[0]), "steps": args.policy_steps, "batch": 8192,
+                "train_s": round(train_s, 3), "ray_gen_s": round(gen_s, 2),
+                "loss_first": float(hist[:20].mean()), "loss_last": float(hist[-100:].mean()),
+                "heldout_records": int(len(ye)),
+                "u_half_accuracy": {"closest_first": float(((fe12 > 0).astype(int) == (ye >> 1)).mean()),
+                                    "learned": float(((np.argmax(z, axis=1) >> 1) == (ye >> 1)).mean())},
+                "grandchild_accuracy": float((np.argmax(z, axis=1) == ye).mean())}
 
 
 def bench_animation(args, torch, ccs, scenes):

@@ -25,6 +25,8 @@ from __future__ import annotations
 import dataclasses
 import math
 
+import os
+
 import numpy as np
 
 SEED = 1811035
@@ -350,8 +352,10 @@ def instanced_scene(n_objects: int = 2000, n_theta: int = 25, n_phi: int = 20,
     cp = np.empty((n_objects * per, 20, 3), dtype=np.float64)
     for b in range(0, n_objects, 128):  # object chunks keep the temporaries cache-sized
         e = min(n_objects, b + 128)
-        cg = np.einsum("oab,otpb->otpa", rot[b:e], cages[b:e]) * scale[b:e, None, None, None] \
-            + centre[b:e, None, None, :]
+        rb, cb = rot[b:e, None, None], cages[b:e]
+        cg = np.stack([rb[..., a, 0] * cb[..., 0] + rb[..., a, 1] * cb[..., 1] + rb[..., a, 2] * cb[..., 2]
+                       for a in range(3)], axis=-1)
+        cg = cg * scale[b:e, None, None, None] + centre[b:e, None, None, :]
         cp[b * per:e * per] = to_twenty(bspline_to_bezier(cg).reshape(-1, 16, 3))
     n = cp.shape[0]
     types = np.zeros(n, dtype=np.uint8)
@@ -381,21 +385,32 @@ def sample_indices(n: int, k: int, seed: int = SEED) -> np.ndarray:
 
 # -------------------------------------------------------------- animation
 def animate(cp: np.ndarray, frame: int, n_frames: int = 16, seed: int = STREAM_ANIMATION,
-            amp_rel: float = 0.05) -> np.ndarray:
+            amp_rel: float = 0.05, chunk: int = 1 << 18) -> np.ndarray:
     """Frame ``frame`` of a seeded animation: every control point x (all 20 slots) moves by
     A (sin(k1.x + 2 pi f/F + p1), sin(k2.x + 2 pi f/F + p2), sin(k3.x + 2 pi f/F + p3)),
     A = amp_rel * mean patch cell, k_i = 2 pi * seeded unit vectors, p_i seeded.  The
     displacement is a function of the rest position, so points shared by neighbouring
-    patches move together and seams stay closed."""
+    patches move together and seams stay closed.  Patches are processed in chunks."""
     s = [substream(seed, k) for k in range(2)]
     k = normal(s[0], 9).reshape(3, 3)
     k = 2.0 * np.pi * k / np.linalg.norm(k, axis=1, keepdims=True)
     phase = 2.0 * np.pi * uniform(s[1], 3)
-    c = cp.astype(np.float64)
-    amp = amp_rel * float(np.mean(patch_cell(c[:, :16])))
-    x = c.reshape(-1, 3)
-    arg = x @ k.T + phase[None, :] + 2.0 * np.pi * frame / n_frames
-    return (x + amp * np.sin(arg)).reshape(cp.shape).astype(np.float32)
+    n = cp.shape[0]
+    cell = 0.0
+    for b in range(0, n, chunk):
+        cell += float(np.sum(patch_cell(cp[b:b + chunk, :16].astype(np.float64))))
+    amp = amp_rel * cell / max(n, 1)
+    out = np.empty(cp.shape, dtype=np.float32)
+
+    def one(b):
+        x = cp[b:b + chunk].astype(np.float64).reshape(-1, 3)
+        arg = x @ k.T + phase[None, :] + 2.0 * np.pi * frame / n_frames
+        out[b:b + chunk] = (x + amp * np.sin(arg)).reshape(-1, 20, 3).astype(np.float32)
+
+    from concurrent.futures import ThreadPoolExecutor  # elementwise: any chunk order gives the same bits
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        list(ex.map(one, range(0, n, chunk)))
+    return out
 
 
 @dataclasses.dataclass
@@ -458,3 +473,39 @@ def policy_training_rays(n: int, seed: int = STREAM_MLP) -> np.ndarray:
     same recipe as its diffuse workload, from a stream of their own."""
     cp, types = torus_scene()
     return surface_bounce_rays(cp, types, 12, (0.0, -3.2, 2.0), n, seed=substream(seed, 100))
+
+
+# ----------------------------------------------------------- combined run
+@dataclasses.dataclass
+class Combined:
+    name: str
+    cp: np.ndarray          # frame 0 (rest) control points, (n, 20, 3) float32
+    types: np.ndarray
+    leaf_depth: int
+    eye: tuple
+    primary: np.ndarray     # (W*H, 8) float32
+    n_frames: int
+    bounces: int
+
+    def frame(self, f: int) -> np.ndarray:
+        return animate(self.cp, f, self.n_frames)
+
+    def bounce_uniforms(self, frame: int, bounce: int, n: int) -> np.ndarray:
+        """Seeded uniforms (n x 2) for secondary-ray generation (ccs_bounce)."""
+        return uniform(substream(STREAM_BOUNCE, 1000 + 16 * frame + bounce), 2 * n).astype(np.float32)
+
+    @property
+    def diameter(self) -> float:
+        c = self.cp.reshape(-1, 3)
+        return float(np.linalg.norm(c.max(axis=0).astype(np.float64) - c.min(axis=0)))
+
+
+def config5(n_objects: int = 16000, width: int = 3840, height: int = 2160, n_frames: int = 8,
+            bounces: int = 3) -> Combined:
+    """8,000,000 patches (16000 objects x 500, 30% Gregory) in [-80, 80]^3, L=10,
+    3840x2160 primary rays from (0,-220,60), each followed by `bounces` diffuse
+    bounces generated from the hits (ccs_bounce), over `n_frames` animation frames."""
+    cp, types = instanced_scene(n_objects, gregory_frac=0.30, extent=80.0)
+    eye = (0.0, -220.0, 60.0)
+    prim = pinhole_rays(eye, (0, 0, 0), (0, 0, 1), 50.0, width, height)
+    return Combined(f"instanced-{cp.shape[0]}p-L10-anim{n_frames}", cp, types, 10, eye, prim, n_frames, bounces)
