@@ -90,9 +90,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["instanced1m", "torus512", "anim512"], default="instanced1m",
+    ap.add_argument("--workload", choices=["instanced1m", "torus512", "anim512", "combined8m"],
+                    default="instanced1m",
                     help="anim512: the 512-patch torus animated over 16 frames, every frame refit and all "
-                         "frames' uneven ray batches in one launch, the frame loop replayed as a HIP graph")
+                         "frames' uneven ray batches in one launch, the frame loop replayed as a HIP graph; "
+                         "combined8m: 8M patches, 8 animation frames, 3840x2160 primary rays and 3 diffuse "
+                         "bounces generated from the hits, closest-first and learned order")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-counters", action="store_true", help="skip the counted launch (roofline)")
@@ -132,6 +135,8 @@ def main():
         del src, dst
     if args.workload == "anim512":
         return bench_animation(args, torch, ccs, scenes)
+    if args.workload == "combined8m":
+        return bench_combined(args, torch, ccs, scenes)
     t0 = time.time()
     w = scenes.config2() if args.workload == "instanced1m" else scenes.config1()
     gen_s = time.time() - t0
@@ -479,6 +484,125 @@ def bench_animation(args, torch, ccs, scenes):
                    "ms_median": float(np.median(laps))},
         "roofline": None, "cpu_baseline": cpu, "parity_sample": parity, "source_hash": source_hash()}),
         flush=True)
+
+
+def bench_combined(args, torch, ccs, scenes):
+    """8M patches over 8 frames: per step every frame is refit, then one launch
+    intersects the primary rays of all frames, and each of 3 bounce levels
+    generates secondary rays from the previous level's hits (per frame) and
+    intersects them in one launch.  Closest-first and learned order are timed."""
+    from paper_1811_03510_amd import autotune
+    t0 = time.time()
+    w = scenes.config5()
+    log(f"workload {w.name}: {w.cp.shape[0]} patches ({int(w.types.sum())} Gregory), {len(w.primary)} primary "
+        f"rays, {w.n_frames} frames, {w.bounces} bounces; generated in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
+    scene.set_frames(w.n_frames)
+    cps = []
+    for f in range(w.n_frames):
+        cps.append(torch.from_numpy(w.frame(f)).cuda())
+        scene.refit_frame(f, cps[-1])
+    torch.cuda.synchronize()
+    info = scene.info()
+    log(f"scene + frames ready in {time.time() - t0:.1f} s: BVH depth {info['bvh_depth']}, "
+        f"{info['device_bytes'] / 2**30:.2f} GiB")
+    F, B, n = w.n_frames, w.bounces, len(w.primary)
+    prim = torch.from_numpy(w.primary).cuda()
+    rays = [[prim] * F] + [[torch.empty_like(prim) for _ in range(F)] for _ in range(B)]
+    hits = [[torch.empty((n, 4), dtype=torch.float32, device="cuda") for _ in range(F)] for _ in range(B + 1)]
+    unif = [[torch.from_numpy(w.bounce_uniforms(f, b, n)).cuda() for f in range(F)] for b in range(B)]
+    ray_bytes = sum(t.numel() * 4 for lvl in rays[1:] for t in lvl) + prim.numel() * 4
+    hit_bytes = sum(t.numel() * 4 for lvl in hits for t in lvl)
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        for f in range(F):
+            scene.refit_frame(f, cps[f])
+        for b in range(B + 1):
+            if b > 0:
+                for f in range(F):
+                    scene.bounce(rays[b - 1][f], hits[b - 1][f], unif[b - 1][f], out=rays[b][f], frame=f)
+            if evs:
+                evs[b].record(stream)
+            scene.intersect_batched([(f, rays[b][f], hits[b][f]) for f in range(F)])
+            if evs:
+                evs[b + 1 + B].record(stream)
+
+    def run(label):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * B + 2)] for _ in range(args.steps)]
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for k in range(args.steps):
+            step(evs[k])
+        z.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(z) / args.steps
+        lvl = [float(np.median([e[b].elapsed_time(e[b + 1 + B]) for e in evs])) for b in range(B + 1)]
+        total = F * (B + 1) * n
+        active = [float((hits[b][0][:, 0] < float("inf")).float().mean().item()) for b in range(B + 1)]
+        res = {"ms_per_step": ms, "mrays_per_s": total / (ms * 1e-3) / 1e6, "launch": scene.get_launch(),
+               "intersect_ms_per_level": lvl,
+               "mrays_per_s_per_level": [F * n / (t * 1e-3) / 1e6 for t in lvl],
+               "hit_fraction_frame0_per_level": active}
+        log(f"{label}: {ms:.1f} ms/step -> {res['mrays_per_s']:.1f} MRays/s; levels {[round(t, 2) for t in lvl]} ms")
+        return res
+
+    variants = {}
+    b0 = [(f, rays[0][f], hits[0][f]) for f in range(F)]
+    if args.autotune:
+        autotune.tuned(scene, b0, name=w.name)
+    variants["batched"] = run("closest-first")
+    h_plain = [[hits[b][f][:4096].cpu().numpy() for f in (0, F - 1)] for b in range(B + 1)]
+    samples = [[rays[b][f][:4096].cpu().numpy() for f in (0, F - 1)] for b in range(B + 1)]
+    if info["bvh_depth"] < 37:
+        policy, pstats = train_policy(args, torch, ccs, scenes)
+        scene.set_policy(policy)
+        if args.autotune:
+            autotune.tuned(scene, b0, name=w.name, learned=True)
+        variants["learned_batched"] = run("learned order")
+        variants["learned_batched"]["policy"] = pstats
+        scene.set_policy(None)
+    cpu, parity = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.parity import gate
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+        threads = min(threads, os.cpu_count() or threads)
+        parity, osec, nsamp = {}, 0.0, 0
+        for j, f in enumerate((0, F - 1)):
+            t0 = time.time()
+            osc = oracle.Scene(w.frame(f), w.types, w.leaf_depth)
+            log(f"oracle scene of frame {f} in {time.time() - t0:.1f} s")
+            for b in range(B + 1):
+                r = samples[b][j]
+                t0 = time.time()
+                o = osc.intersect(r, nthreads=threads)
+                osec += time.time() - t0
+                nsamp += len(r)
+                g = gate(h_plain[b][j], o, r, osc, w.diameter, w.leaf_depth, label=f"frame{f}-level{b}")
+                parity[f"frame{f}_level{b}"] = {"rays": g["n"], "same_hit_and_patch": g["id_rate"], "ok": g["ok"]}
+            del osc
+        cpu = {"value": round(nsamp / osec / 1e6, 4), "unit": "MRays/s", "cores": threads, "kind": "oracle",
+               "sample": f"the first 4096 rays of every level of frames 0 and {F - 1} (oracle BVH builds excluded)"}
+        log(f"cpu baseline {cpu['value']} MRays/s; parity {parity}")
+    head = "batched"
+    print(json.dumps({
+        "metric": "MRays/s combined run: 8M patches, 8 frames, primary + 3 diffuse bounces",
+        "value": round(variants[head]["mrays_per_s"], 3), "unit": "MRays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(variants[head]["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
+        "config": {"workload": f"{w.name}: {w.cp.shape[0]} patches, {F} frames, {n} primary rays + {B} bounces "
+                               f"per frame ({F * (B + 1) * n} rays per step)", "leaf_depth": w.leaf_depth,
+                   "variant": "closest-first order, batched over frames"},
+        "variants": variants, "roofline": None, "cpu_baseline": cpu, "parity_sample": parity,
+        "device_memory_gib": {"scene_all_frames": round(info["device_bytes"] / 2**30, 3),
+                              "frame_control_points": round(sum(c.numel() * 4 for c in cps) / 2**30, 3),
+                              "rays": round(ray_bytes / 2**30, 3), "hits": round(hit_bytes / 2**30, 3)},
+        "source_hash": source_hash()}), flush=True)
 
 
 if __name__ == "__main__":

@@ -113,9 +113,10 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out);
 /* Moves the control points of an existing scene (animation playback, the use
  * case named in the abstract).  Same n, same tags, same layout as at creation.
  * Anchors stay at their creation values.  On the GPU: anchored points and patch
- * boxes are recomputed and the BVH node boxes are refitted bottom-up; the
- * topology is unchanged.  Asynchronous on `stream`; device input must stay
- * valid until the stream passes this call.  Host input is copied before return.
+ * boxes are recomputed, then the BVH node boxes level by level from the deepest
+ * (one launch per level); the topology is unchanged.  Asynchronous on `stream`;
+ * device input must be 16-byte aligned and stay valid until the stream passes
+ * this call.  Host input is copied before return.
  * Host input is scanned for non-finite values (CCS_ERR_INVALID_ARG); device input
  * is not scanned (non-finite points then give unspecified hits, never a fault). */
 ccs_status ccs_refit(ccs_scene* scene, const float* control_points, int32_t location, void* stream);
@@ -202,6 +203,12 @@ ccs_status ccs_scene_get_launch(const ccs_scene* scene, ccs_launch_params* param
  * of n elements; out_rays may not alias rays.  Asynchronous on `stream`. */
 ccs_status ccs_bounce(const ccs_scene* scene, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                       uint32_t n, ccs_ray* out_rays, void* stream);
+
+/* As ccs_bounce, with the geometry of animation frame `frame` (hits from a
+ * ccs_intersect_batched batch on that frame).  CCS_ERR_INVALID_ARG for a frame
+ * outside the scene's frames. */
+ccs_status ccs_bounce_frame(const ccs_scene* scene, uint32_t frame, const ccs_ray* rays, const ccs_hit* hits,
+                            const float* uniforms, uint32_t n, ccs_ray* out_rays, void* stream);
 
 /* ---------------------------------------------------- learned child ordering
  * Alg. 3 visits the two halves of a split closest box first (Sec. 3.3).  A

@@ -24,7 +24,8 @@ COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "
 EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_counted", "ccs_bounce",
            "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
            "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched",
-           "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train")
+           "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train",
+           "ccs_bounce_frame")
 MAX_BATCHES = 32
 POLICY_PARAMS = 1732
 NO_LABEL = 255
@@ -80,6 +81,7 @@ def lib():
         L.ccs_intersect.argtypes = [vp, vp, u32, vp, vp]
         L.ccs_intersect_counted.argtypes = [vp, vp, u32, vp, vp, vp]
         L.ccs_bounce.argtypes = [vp, vp, vp, vp, u32, vp, vp]
+        L.ccs_bounce_frame.argtypes = [vp, u32, vp, vp, vp, u32, vp, vp]
         L.ccs_scene_info_get.argtypes = [vp, C.POINTER(SceneInfo)]
         L.ccs_scene_destroy.argtypes = [vp]
         L.ccs_scene_destroy.restype = None
@@ -263,14 +265,18 @@ class Scene:
         self._refit_keep = cp  # device input must outlive the queued work
         _check(lib().ccs_refit(self._h, _ptr(cp), CCS_DEVICE if cp.is_cuda else CCS_HOST, _stream(stream)))
 
-    def bounce(self, rays, hits, uniforms, out=None, stream=None):
+    def bounce(self, rays, hits, uniforms, out=None, stream=None, frame: int = 0):
+        """Secondary rays from hits (uniforms: (N, 2) float32 in [0, 1)) on the given frame."""
         import torch
         r = self._rays(rays)
         n = r.shape[0]
+        h, u = torch.as_tensor(hits), torch.as_tensor(uniforms)
+        if not (h.is_cuda and u.is_cuda and h.is_contiguous() and u.is_contiguous() and h.numel() == 4 * n
+                and u.numel() == 2 * n and h.dtype == torch.float32 and u.dtype == torch.float32):
+            raise ValueError("hits (N, 4) and uniforms (N, 2) must be contiguous float32 CUDA tensors")
         if out is None:
             out = torch.empty_like(r)
-        _check(lib().ccs_bounce(self._h, _ptr(r), _ptr(hits.contiguous()), _ptr(uniforms.contiguous()), n,
-                                _ptr(out), _stream(stream)))
+        _check(lib().ccs_bounce_frame(self._h, int(frame), _ptr(r), _ptr(h), _ptr(u), n, _ptr(out), _stream(stream)))
         return out
 
 

@@ -42,6 +42,7 @@ struct ccs_scene {
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   double build_seconds = 0.0;
   float* cp_stage = nullptr;  // device staging buffer for host refit input
+  std::vector<uint32_t> level_offsets;  // nodes of depth d: level_nodes[level_offsets[d] .. level_offsets[d+1])
   uint32_t* queues = nullptr;  // kQueueSlots ray-queue counters
   std::atomic<uint32_t> next_queue{0};
   ccs_launch_params launch{0, 16, 1, 16, 2, 8};
@@ -271,15 +272,31 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
   D.n_nodes = n_nodes;
   D.leaf_depth = (int)desc->leaf_depth;
   float4* nodes = nullptr;
-  uint32_t *perm = nullptr, *invp = nullptr, *arr = nullptr;
+  uint32_t *perm = nullptr, *invp = nullptr, *lvl = nullptr;
   int32_t *lpar = nullptr, *npar = nullptr;
   float* drec = nullptr;
   if ((st = dev_alloc(s, &nodes, (size_t)n_nodes * 4)) != CCS_OK || (st = dev_alloc(s, &drec, recs.size())) != CCS_OK ||
       (st = dev_alloc(s, &perm, n)) != CCS_OK || (st = dev_alloc(s, &invp, n)) != CCS_OK ||
       (st = dev_alloc(s, &lpar, n)) != CCS_OK || (st = dev_alloc(s, &npar, n_nodes)) != CCS_OK ||
-      (st = dev_alloc(s, &arr, n_nodes)) != CCS_OK || (st = dev_alloc(s, &s->queues, kQueueSlots)) != CCS_OK) {
+      (st = dev_alloc(s, &lvl, n_nodes)) != CCS_OK || (st = dev_alloc(s, &s->queues, kQueueSlots)) != CCS_OK) {
     free_scene(s);
     return st;
+  }
+  // nodes grouped by depth for the level-by-level refit (parents precede children
+  // in the depth-first layout, so one pass gives every depth)
+  std::vector<uint32_t> node_depth(n_nodes, 0), level_nodes(n_nodes);
+  uint32_t max_d = 0;
+  for (uint32_t k = 1; k < n_nodes; ++k) {
+    const int32_t link = bvh.node_parent[k];
+    node_depth[k] = link < 0 ? 0 : node_depth[(uint32_t)link >> 1] + 1;
+    max_d = std::max(max_d, node_depth[k]);
+  }
+  s->level_offsets.assign(n_nodes ? max_d + 2 : 1, 0);
+  for (uint32_t k = 0; k < n_nodes; ++k) s->level_offsets[node_depth[k] + 1]++;
+  for (size_t d = 1; d < s->level_offsets.size(); ++d) s->level_offsets[d] += s->level_offsets[d - 1];
+  {
+    std::vector<uint32_t> fill(s->level_offsets.begin(), s->level_offsets.end() - 1);
+    for (uint32_t k = 0; k < n_nodes; ++k) level_nodes[fill[node_depth[k]]++] = k;
   }
   hipStream_t stream = (hipStream_t)desc->stream;
   struct Up {
@@ -291,7 +308,8 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
              {perm, bvh.perm.data(), (size_t)n * 4},
              {invp, inv_perm.data(), (size_t)n * 4},
              {lpar, bvh.leaf_parent.data(), (size_t)n * 4},
-             {npar, bvh.node_parent.data(), (size_t)n_nodes * 4}};
+             {npar, bvh.node_parent.data(), (size_t)n_nodes * 4},
+             {lvl, level_nodes.data(), (size_t)n_nodes * 4}};
   for (const Up& u : ups) {
     if (u.bytes == 0) continue;
     e = hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, stream);
@@ -311,7 +329,7 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
   D.inv_perm = invp;
   D.leaf_parent = lpar;
   D.node_parent = npar;
-  D.arrivals = arr;
+  D.level_nodes = lvl;
   int cus = 0;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) {
@@ -372,6 +390,8 @@ ccs_status ccs_refit_frame(ccs_scene* s, uint32_t frame, const float* control_po
   if (!control_points) return fail(CCS_ERR_INVALID_ARG, "control_points is NULL");
   if (location != CCS_HOST && location != CCS_DEVICE)
     return fail(CCS_ERR_INVALID_ARG, "location must be CCS_HOST or CCS_DEVICE");
+  if (location == CCS_DEVICE && (reinterpret_cast<uintptr_t>(control_points) & 15u) != 0)
+    return fail(CCS_ERR_INVALID_ARG, "device control_points must be 16-byte aligned");
   const size_t count = (size_t)s->dev.n_patches * 60;
   hipStream_t st = (hipStream_t)stream;
   const float* src = control_points;
@@ -390,7 +410,7 @@ ccs_status ccs_refit_frame(ccs_scene* s, uint32_t frame, const float* control_po
   ccs::DeviceScene f = s->dev;
   f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
   f.nodes = s->dev.nodes + frame * s->dev.frame_node_f4;
-  hipError_t e = ccs::launch_refit(f, src, st);
+  hipError_t e = ccs::launch_refit(f, src, s->level_offsets.data(), (uint32_t)s->level_offsets.size() - 1, st);
   if (e != hipSuccess) return hip_fail(e, "refit launch");
   return CCS_OK;
 }
@@ -482,16 +502,25 @@ ccs_status ccs_scene_get_launch(const ccs_scene* s, ccs_launch_params* p) {
   return CCS_OK;
 }
 
-ccs_status ccs_bounce(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms, uint32_t n,
-                      ccs_ray* out_rays, void* stream) {
+ccs_status ccs_bounce_frame(const ccs_scene* s, uint32_t frame, const ccs_ray* rays, const ccs_hit* hits,
+                            const float* uniforms, uint32_t n, ccs_ray* out_rays, void* stream) {
   g_error.clear();
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (frame >= s->dev.n_frames) return fail(CCS_ERR_INVALID_ARG, "frame out of range");
   if (n == 0) return CCS_OK;
   if (!rays || !hits || !uniforms || !out_rays) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
   if ((const void*)out_rays == (const void*)rays) return fail(CCS_ERR_INVALID_ARG, "out_rays aliases rays");
-  hipError_t e = ccs::launch_bounce(s->dev, rays, hits, uniforms, n, out_rays, (hipStream_t)stream);
+  ccs::DeviceScene f = s->dev;
+  f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
+  f.nodes = s->dev.nodes + frame * s->dev.frame_node_f4;
+  hipError_t e = ccs::launch_bounce(f, rays, hits, uniforms, n, out_rays, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "bounce launch");
   return CCS_OK;
+}
+
+ccs_status ccs_bounce(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms, uint32_t n,
+                      ccs_ray* out_rays, void* stream) {
+  return ccs_bounce_frame(s, 0, rays, hits, uniforms, n, out_rays, stream);
 }
 
 // ------------------------------------------------------- learned child ordering

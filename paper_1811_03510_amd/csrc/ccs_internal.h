@@ -32,7 +32,7 @@ struct DeviceScene {
   const uint32_t* inv_perm;  // original index -> record
   const int32_t* leaf_parent;  // record -> (node << 1 | side)
   const int32_t* node_parent;  // node -> (parent << 1 | side), -1 for the root
-  uint32_t* arrivals;        // n_nodes counters for the bottom-up refit
+  const uint32_t* level_nodes;  // node indices sorted by depth (refit order; offsets on the host)
   uint32_t n_cus;            // compute units of the device
   uint32_t n_frames;         // frames: copies of recs and node boxes sharing one topology
   size_t frame_rec_floats;   // floats per frame in recs (n_patches * kRecFloats)
@@ -67,7 +67,8 @@ constexpr uint32_t kMaxBvhDepthLearned = 38;
 int max_waves_per_cu(bool counted, bool learned);
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
                             uint32_t waves_per_cu, hipStream_t stream);
-hipError_t launch_refit(const DeviceScene& s, const float* cp_world, hipStream_t stream);
+hipError_t launch_refit(const DeviceScene& s, const float* cp_world, const uint32_t* level_offsets,
+                        uint32_t n_levels, hipStream_t stream);
 hipError_t launch_policy_pack(const float* params, uint2* w, float4* b, hipStream_t stream);
 hipError_t launch_policy_infer(const PolicyDev& P, const float* x, uint32_t n, float* z, hipStream_t stream);
 hipError_t launch_record(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, uint32_t n, float* feats,

@@ -120,6 +120,7 @@ def test_policy_and_batch_entry_points_validate_on_the_host():
     assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None) == ccs.CCS_OK  # no steps
     assert L.ccs_policy_train(None, fake, fake, 100, C.byref(tp), None, None) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_intersect_batched(None, None, 1, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_bounce_frame(None, 0, fake, fake, fake, 4, fake, None) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_scene_set_frames(None, 2) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_refit_frame(None, 0, fake, 1, None) == ccs.CCS_ERR_INVALID_ARG
     p = ccs.LaunchParams(0, 16, 1, 16, 2, 0)

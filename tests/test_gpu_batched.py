@@ -138,3 +138,37 @@ def test_autotuner_picks_a_setting_and_caches_it(anim, scene, tmp_path, monkeypa
     scene.set_launch()
     for a, b in zip(ref, got):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_bounce_on_a_frame_uses_that_frames_geometry(anim, scene):
+    """Secondary rays from hits on frame f follow frame f's surface (oracle on that frame)."""
+    rng = np.random.default_rng(17)
+    f = len(anim.frames) - 1
+    cp = anim.frames[f]
+    n, L = 2000, anim.leaf_depth
+    idx = rng.integers(0, cp.shape[0], n)
+    leaf = 2.0 ** -L
+    u = (rng.integers(0, 1 << L, n) + 0.5) * leaf
+    v = (rng.integers(0, 1 << L, n) + 0.5) * leaf
+    x = S.surface_points(cp, anim.types, idx, u, v)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t = rng.uniform(0.5, 2.0, size=n)
+    rays = np.zeros((n, 8), np.float32)
+    rays[:, :3], rays[:, 4:7], rays[:, 7] = x - t[:, None] * d, d, np.inf
+    hits = np.zeros((n, 4), np.float32)
+    hits[:, 0], hits[:, 2], hits[:, 3] = t, u, v
+    hits[:, 1] = idx.astype(np.uint32).view(np.float32)
+    w = rng.uniform(size=(n, 2)).astype(np.float32)
+    ref = O.Scene(cp, anim.types, L).bounce(rays, hits, w)
+    out = scene.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda(),
+                       frame=f)
+    out0 = scene.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda())
+    out, out0 = out.cpu().numpy().astype(np.float64), out0.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(out[:, :3], ref[:, :3], atol=2e-6 * anim.diameter)
+    np.testing.assert_allclose(out[:, 4:7], ref[:, 4:7], atol=2e-5)
+    assert np.abs(out0[:, :3] - ref[:, :3]).max() > 1e-4  # frame 0's geometry is elsewhere
+    from paper_1811_03510_amd import ccs
+    with pytest.raises(ccs.CcsError):
+        scene.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda(),
+                     frame=len(anim.frames))
