@@ -37,7 +37,8 @@ def lib():
         L.orc_wbar.restype = d
         L.orc_inner_extremes.argtypes = [P(d), d, d, d, d, P(d), P(d)]
         L.orc_calc_points_and_d.argtypes = [P(d), i32, d, d, d, d, P(d), P(d)]
-        L.orc_scene_create.argtypes = [P(C.c_float), P(C.c_uint8), u32, i32, i32]
+        L.orc_scene_create.argtypes = [P(C.c_float), P(C.c_uint8), u32, i32, i32, i32]
+        L.orc_patch_frame.argtypes = [vp, u32, P(d)]
         L.orc_scene_create.restype = vp
         L.orc_scene_destroy.argtypes = [vp]
         L.orc_scene_nodes.argtypes = [vp]
@@ -122,20 +123,27 @@ def calc_points_and_d(cp20, gregory: bool, u0, u1, v0, v1):
 class Scene:
     """Oracle scene: patches (n, 20, 3) float32, tags (n,) uint8, per-axis leaf depth L."""
 
-    def __init__(self, cp, types, leaf_depth: int, use_bvh: bool = True):
+    def __init__(self, cp, types, leaf_depth: int, use_bvh: bool = True, local_frames: bool = False):
         self.cp = np.ascontiguousarray(cp, dtype=np.float32).reshape(-1, 20, 3)
         self.types = np.ascontiguousarray(types, dtype=np.uint8)
         assert self.types.shape[0] == self.cp.shape[0]
         self.n = self.cp.shape[0]
         self.leaf_depth = int(leaf_depth)
+        self.local_frames = bool(local_frames)
         self._h = lib().orc_scene_create(_p(self.cp, C.c_float), _p(self.types, C.c_uint8), self.n,
-                                         self.leaf_depth, int(use_bvh))
+                                         self.leaf_depth, int(use_bvh), int(self.local_frames))
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
             lib().orc_scene_destroy(h)
             self._h = None
+
+    def patch_frame(self, k: int) -> np.ndarray:
+        """Rows (3 x 3) of patch k's local frame (the identity unless local_frames)."""
+        r = np.zeros(9)
+        lib().orc_patch_frame(self._h, int(k), _p(r, C.c_double))
+        return r.reshape(3, 3)
 
     @property
     def n_nodes(self) -> int:

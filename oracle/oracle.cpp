@@ -60,6 +60,7 @@ struct Patch {
   V3 cp[20];
   bool gregory;
   V3 lo, hi;  // hull of the 16 (Bezier) or 20 (Gregory) points
+  double pad = 0.0;  // every subdivision box grown by this on all sides (patch-local frames)
 };
 
 struct Ray {
@@ -286,14 +287,15 @@ static Bound calc_points_and_d_int(const Patch& P, uint32_t pu, uint32_t pv, uin
   return calc_points_and_d(P, pu * kUnit, (pu + su) * kUnit, pv * kUnit, (pv + sv) * kUnit);
 }
 
-static void grid_box(const Grid& g, V3 d, V3* lo, V3* hi) {
+static void grid_box(const Grid& g, V3 d, double pad, V3* lo, V3* hi) {
   V3 a = g.p[0], b = g.p[0];
   for (int s = 1; s < 16; ++s) {
     a = vmin(a, g.p[s]);
     b = vmax(b, g.p[s]);
   }
-  *lo = a;
-  *hi = b + d;
+  const V3 e = {pad, pad, pad};
+  *lo = a - e;
+  *hi = (b + d) + e;
 }
 
 // ------------------------------------------------------------------ slab test
@@ -392,8 +394,8 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
     Grid gl, gr;
     split_half(f.g, f.axis, &gl, &gr);
     V3 lol, hil, lor, hir;
-    grid_box(gl, f.d, &lol, &hil);
-    grid_box(gr, f.d, &lor, &hir);
+    grid_box(gl, f.d, P.pad, &lol, &hil);
+    grid_box(gr, f.d, P.pad, &lor, &hir);
     double tl = 0, tr = 0;
     bool hl = slab(r, lol, hil, best.t, &tl);
     bool hr = slab(r, lor, hir, best.t, &tr);
@@ -445,13 +447,50 @@ struct Node {
   uint32_t first, count;  // leaf range into order[]
 };
 
+// Patch-local frame (Sec. 3.4: intersecting in local frames tightens the boxes):
+// rows r0 = unit(p30 - p00), r1 = unit of (p03 - p00) with its r0 part removed,
+// r2 = r0 x r1; the identity for a patch whose u or v edge is degenerate.  A
+// point x maps to (r0.x, r1.x, r2.x), applied to both patch and ray, so ray
+// parameters are unchanged and only the boxes (now in the patch's frame) differ.
+struct Frame3 {
+  V3 r0, r1, r2;
+};
+
 struct Scene {
   std::vector<Patch> patches;
   std::vector<Node> nodes;
   std::vector<uint32_t> order;
   int L;
   bool use_bvh;
+  bool local = false;               // subdivide each patch in its local frame
+  std::vector<Frame3> frames;       // per patch, when local
+  std::vector<Patch> local_patches;  // patches mapped into their frames, when local
 };
+
+static Frame3 local_frame(const Patch& P) {
+  const Frame3 id = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  V3 eu = P.cp[3] - P.cp[0], ev = P.cp[12] - P.cp[0];
+  double lu = std::sqrt(dot(eu, eu)), lv = std::sqrt(dot(ev, ev));
+  if (!(lu > 0.0) || !(lv > 0.0)) return id;
+  V3 r0 = (1.0 / lu) * eu;
+  V3 w = ev - dot(ev, r0) * r0;
+  double lw = std::sqrt(dot(w, w));
+  if (!(lw > 1e-9 * lv)) return id;
+  V3 r1 = (1.0 / lw) * w;
+  return {r0, r1, cross(r0, r1)};
+}
+
+static inline V3 to_frame(const Frame3& F, V3 x) { return {dot(F.r0, x), dot(F.r1, x), dot(F.r2, x)}; }
+
+// The patch and ray that subdivision works on: world ones, or both in the patch's frame.
+static inline const Patch& work_patch(const Scene& S, uint32_t k) {
+  return S.local ? S.local_patches[k] : S.patches[k];
+}
+static inline Ray work_ray(const Scene& S, uint32_t k, const Ray& r) {
+  if (!S.local) return r;
+  const Frame3& F = S.frames[k];
+  return {to_frame(F, r.o), to_frame(F, r.d), r.tmin, r.tmax};
+}
 
 static void load_patch(Patch& P, const float* cp, uint8_t type) {
   P.gregory = type == 1;
@@ -511,7 +550,7 @@ static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
       if (!slab(r, S.patches[k].lo, S.patches[k].hi, best.t, &e)) continue;
       c.cand++;
       c.cand_greg += S.patches[k].gregory;
-      intersect_patch(S.patches[k], k, r, S.L, best, c, nullptr);
+      intersect_patch(work_patch(S, k), k, work_ray(S, k, r), S.L, best, c, nullptr);
     }
     return;
   }
@@ -529,7 +568,7 @@ static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
         if (!slab(r, S.patches[id].lo, S.patches[id].hi, best.t, &e)) continue;
         c.cand++;
         c.cand_greg += S.patches[id].gregory;
-        intersect_patch(S.patches[id], id, r, S.L, best, c, nullptr);
+        intersect_patch(work_patch(S, id), id, work_ray(S, id, r), S.L, best, c, nullptr);
       }
       continue;
     }
@@ -786,12 +825,49 @@ void orc_calc_points_and_d(const double* cp, int gregory, double u0, double u1, 
 }
 
 // ---- scenes ----
-void* orc_scene_create(const float* cp, const uint8_t* types, uint32_t n, int L, int use_bvh) {
+// Rows of patch k's local frame (9 doubles; the identity when the scene is not local).
+void orc_patch_frame(void* s, uint32_t k, double* rows9) {
+  const Scene& S = *(Scene*)s;
+  Frame3 F = S.local ? S.frames[k] : Frame3{{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  const V3 r[3] = {F.r0, F.r1, F.r2};
+  for (int a = 0; a < 3; ++a) {
+    rows9[3 * a] = r[a].x;
+    rows9[3 * a + 1] = r[a].y;
+    rows9[3 * a + 2] = r[a].z;
+  }
+}
+
+// flags bit 0: subdivide in patch-local frames.
+void* orc_scene_create(const float* cp, const uint8_t* types, uint32_t n, int L, int use_bvh, int flags) {
   Scene* S = new Scene();
   S->L = L;
   S->use_bvh = use_bvh != 0;
+  S->local = (flags & 1) != 0;
   S->patches.resize(n);
   for (uint32_t k = 0; k < n; ++k) load_patch(S->patches[k], cp + 60 * (size_t)k, types[k]);
+  if (S->local) {
+    S->frames.resize(n);
+    S->local_patches.resize(n);
+    for (uint32_t k = 0; k < n; ++k) {
+      const Patch& P = S->patches[k];
+      const Frame3 F = local_frame(P);
+      Patch Q = P;
+      for (int sl = 0; sl < 20; ++sl) Q.cp[sl] = to_frame(F, P.cp[sl]);
+      const int m = Q.gregory ? 20 : 16;
+      Q.lo = Q.hi = Q.cp[0];
+      for (int sl = 1; sl < m; ++sl) {
+        Q.lo = vmin(Q.lo, Q.cp[sl]);
+        Q.hi = vmax(Q.hi, Q.cp[sl]);
+      }
+      // Sec. 3.4: in a patch's own frame, corners and straight edges lie on box faces
+      // shared with neighbouring patches, where rounding can open gaps; every box is
+      // grown by 2^-19 of the patch's largest extent in its frame to close them
+      const V3 ext = Q.hi - Q.lo;
+      Q.pad = std::ldexp(std::max(ext.x, std::max(ext.y, ext.z)), -19);
+      S->frames[k] = F;
+      S->local_patches[k] = Q;
+    }
+  }
   S->order.resize(n);
   for (uint32_t k = 0; k < n; ++k) S->order[k] = k;
   if (S->use_bvh && n > 0) build_node(*S, 0, n);
@@ -837,7 +913,7 @@ int orc_trace_patch(void* s, uint32_t patch, const float* ray8, double cap, uint
   Best b = {cap, kNoHit, 0.0, 0.0};
   Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<Split> tr;
-  if (ray_valid(r)) intersect_patch(S.patches[patch], patch, r, S.L, b, c, &tr);
+  if (ray_valid(r)) intersect_patch(work_patch(S, patch), patch, work_ray(S, patch, r), S.L, b, c, &tr);
   int n = (int)std::min<size_t>(tr.size(), (size_t)max_seq);
   for (int k = 0; k < n; ++k) {
     seq[4 * k] = tr[k].pu; seq[4 * k + 1] = tr[k].pv; seq[4 * k + 2] = tr[k].su; seq[4 * k + 3] = tr[k].sv;
@@ -935,9 +1011,9 @@ void orc_bounce(void* s, const float* rays, const float* hits, const float* unif
     // the leaf domain containing (u, v)
     uint32_t pu = std::min((uint32_t)std::floor(hu / kUnit) & ~(leaf - 1), kFull - leaf);
     uint32_t pv = std::min((uint32_t)std::floor(hv / kUnit) & ~(leaf - 1), kFull - leaf);
-    Bound b = calc_points_and_d_int(P, pu, pv, leaf, leaf);
+    Bound b = calc_points_and_d_int(work_patch(S, pid), pu, pv, leaf, leaf);  // box in the frame subdivision uses
     V3 lo, hi;
-    grid_box(b.q, b.d, &lo, &hi);
+    grid_box(b.q, b.d, work_patch(S, pid).pad, &lo, &hi);
     double off = (hi.x - lo.x) + (hi.y - lo.y) + (hi.z - lo.z);
     V3 org = x + off * nn;
     double u1 = uniforms[2 * (size_t)i], u2 = uniforms[2 * (size_t)i + 1];
@@ -970,8 +1046,8 @@ static int ctz32(uint32_t x) {
 int orc_trace_patch_alg3(void* s, uint32_t patch, const float* ray8, double cap, uint32_t* seq, int max_seq,
                          double* hit4) {
   const Scene& S = *(Scene*)s;
-  const Patch& P = S.patches[patch];
-  Ray r = load_ray(ray8);
+  const Patch& P = work_patch(S, patch);
+  Ray r = work_ray(S, patch, load_ray(ray8));
   hit4[0] = cap;
   hit4[1] = (double)kNoHit;
   hit4[2] = hit4[3] = 0.0;
@@ -1002,8 +1078,8 @@ int orc_trace_patch_alg3(void* s, uint32_t patch, const float* ray8, double cap,
       Grid gl, gr;
       split_half(p, axis, &gl, &gr);
       V3 lol, hil, lor, hir;
-      grid_box(gl, d, &lol, &hil);
-      grid_box(gr, d, &lor, &hir);
+      grid_box(gl, d, P.pad, &lol, &hil);
+      grid_box(gr, d, P.pad, &lor, &hir);
       double tl = 0, tr = 0;
       bool hl = slab(r, lol, hil, best.t, &tl), hr = slab(r, lor, hir, best.t, &tr);
       if (hl || hr) {
@@ -1061,27 +1137,29 @@ int orc_trace_patch_alg3(void* s, uint32_t patch, const float* ray8, double cap,
 // Ancestors are not tested.  Returns +inf when the box is missed.
 double orc_leaf_entry(void* s, uint32_t patch, const float* ray8, uint32_t pu, uint32_t pv) {
   const Scene& S = *(Scene*)s;
-  const Patch& P = S.patches[patch];
-  Ray r = load_ray(ray8);
+  const Patch& P = work_patch(S, patch);
+  Ray r = work_ray(S, patch, load_ray(ray8));
   const uint32_t leaf = kFull >> S.L;
   uint32_t ppv = pv & ~(2 * leaf - 1);
   Bound b = calc_points_and_d_int(P, pu, ppv, leaf, 2 * leaf);
   Grid gl, gr;
   split_half(b.q, 1, &gl, &gr);
   V3 lo, hi;
-  grid_box((pv & leaf) ? gr : gl, b.d, &lo, &hi);
+  grid_box((pv & leaf) ? gr : gl, b.d, P.pad, &lo, &hi);
   double e;
   if (!ray_valid(r) || !slab(r, lo, hi, std::numeric_limits<double>::infinity(), &e))
     return std::numeric_limits<double>::infinity();
   return e;
 }
 
-// Box [lo, hi] (6 doubles) of a domain's lower grid plus displacement (calcPointsAndD).
+// Box [lo, hi] (6 doubles) of a domain's lower grid plus displacement
+// (calcPointsAndD), in the frame subdivision uses (the patch's, when local).
 void orc_domain_box(void* s, uint32_t patch, uint32_t pu, uint32_t pv, uint32_t su, uint32_t sv, double* box6) {
   const Scene& S = *(Scene*)s;
-  Bound b = calc_points_and_d_int(S.patches[patch], pu, pv, su, sv);
+  const Patch& P = work_patch(S, patch);
+  Bound b = calc_points_and_d_int(P, pu, pv, su, sv);
   V3 lo, hi;
-  grid_box(b.q, b.d, &lo, &hi);
+  grid_box(b.q, b.d, P.pad, &lo, &hi);
   box6[0] = lo.x; box6[1] = lo.y; box6[2] = lo.z; box6[3] = hi.x; box6[4] = hi.y; box6[5] = hi.z;
 }
 

@@ -68,8 +68,9 @@ def test_host_validation_errors():
         c2[2, 7, 1] = v
         st, msg, _ = create(host_desc(c2, ty))
         assert st == ccs.CCS_ERR_INVALID_ARG and "finite" in msg
-    st, msg, _ = create(host_desc(cp, ty, flags=1))
-    assert st == ccs.CCS_ERR_UNSUPPORTED
+    for flags in (2, 0x80000000):  # bit 0 (local frames) is the only flag
+        st, msg, _ = create(host_desc(cp, ty, flags=flags))
+        assert st == ccs.CCS_ERR_UNSUPPORTED and "flags" in msg
     st, msg, _ = create(host_desc(cp, ty, location=7))
     assert st == ccs.CCS_ERR_INVALID_ARG
 

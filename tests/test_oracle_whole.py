@@ -24,7 +24,16 @@ def rays_at_patches(cp, types, n, rng, spread=3.0):
     return r, idx
 
 
-def test_bit_trail_loop_visits_the_recursion_sequence(c1, c1_oracle):
+@pytest.fixture(scope="module", params=["world", "local"])
+def oracle_any(request, c1, c1_oracle):
+    """The oracle in world coordinates and with patch-local frames (Sec. 3.4)."""
+    if request.param == "world":
+        return c1_oracle
+    return O.Scene(c1.cp, c1.types, c1.leaf_depth, local_frames=True)
+
+
+def test_bit_trail_loop_visits_the_recursion_sequence(c1, oracle_any):
+    c1_oracle = oracle_any
     """Alg. 3 (pos/size/trail registers, ctz backtracking) and the explicit-stack
     recursion produce identical split sequences and hits on random ray-patch pairs."""
     rng = np.random.default_rng(11)
@@ -62,7 +71,8 @@ def test_counters_are_consistent(c1, c1_oracle):
 
 
 @pytest.mark.slow
-def test_dense_tessellation_agrees_within_the_method_error_bound(c1, c1_oracle):
+def test_dense_tessellation_agrees_within_the_method_error_bound(c1, oracle_any):
+    c1_oracle = oracle_any
     L = c1.leaf_depth
     sel_p = S.sample_indices(len(c1.primary), 768, seed=5)
     sel_d = S.sample_indices(len(c1.diffuse), 768, seed=6)
@@ -113,7 +123,8 @@ def test_dense_tessellation_agrees_within_the_method_error_bound(c1, c1_oracle):
     assert good > 400
 
 
-def test_rays_through_shared_edges_and_corners_never_miss(c1, c1_oracle):
+def test_rays_through_shared_edges_and_corners_never_miss(c1, oracle_any):
+    c1_oracle = oracle_any
     rng = np.random.default_rng(21)
     nv = 16
     rays, targets = [], []
