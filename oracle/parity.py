@@ -12,7 +12,13 @@ excused only when the paper's error model explains it:
              (shared edges); a different leaf of the same patch is never a seam;
   * graze -- the ray only clips the leaf box the side that hit reported: its path
              inside that box is shorter than 1e-3 of the box diagonal (plus
-             1e-6 (t + 1) of rounding): silhouettes, box edges and corners.
+             1e-6 (t + 1) of rounding): silhouettes, box edges and corners;
+  * tangent -- same patch, |dt| within tolerance, the ray within 1.2 degrees of
+             tangent to the surface at the oracle's hit (|cos| < 0.02), and the
+             surface at the GPU's (u, v) within the GPU leaf box's diagonal of the
+             ray: along a nearly tangent ray every leaf the ray grazes is a hit to
+             the method's error bound (Sec. 3: the leaf box bounds the error), and
+             rounding moves the first one by its size over |cos|.
 The gate: identical hit/miss and patch id on >= 99.99 % of the rays of a class,
 and every disagreement (in hit/miss, patch, t, u or v) excused.
 """
@@ -21,6 +27,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import Scene  # noqa: F401  (type of the oracle scene argument)
+from . import patch_eval
 
 NO_HIT = 0xFFFFFFFF
 
@@ -59,7 +66,7 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
     close = same & dt_ok & (np.abs(gpu[:, 2] - ora["u"]) <= tol_uv) & \
         (np.abs(gpu[:, 3] - ora["v"]) <= tol_uv)
     match = both_miss | close
-    kinds = {"tie": 0, "seam": 0, "graze": 0, "hard": 0}
+    kinds = {"tie": 0, "seam": 0, "graze": 0, "tangent": 0, "hard": 0}
     hard = []
     for k in np.where(~match)[0]:
         ray = rays[k]
@@ -77,6 +84,20 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
             if np.linalg.norm(xg - xo) <= tol_t or near_edge(gpu[k, 2], gpu[k, 3]) or \
                     near_edge(ora["u"][k], ora["v"][k]):
                 kind = "seam"
+        if kind == "hard" and g_hit[k] and o_hit[k] and gid[k] == oid[k] and dt_ok[k]:
+            pid = int(gid[k])
+            cp, greg = osc.cp[pid], bool(osc.types[pid])
+            o64, d64 = ray[:3].astype(np.float64), ray[4:7].astype(np.float64)
+            dn = d64 / np.linalg.norm(d64)
+            _, fu, fv = patch_eval(cp, greg, float(ora["u"][k]), float(ora["v"][k]))
+            nrm = np.cross(fu, fv)
+            cosv = abs(np.dot(nrm, dn)) / max(np.linalg.norm(nrm), 1e-300)
+            if cosv < 0.02:
+                fg = patch_eval(cp, greg, float(gpu[k, 2]), float(gpu[k, 3]))[0]
+                dist = np.linalg.norm(np.cross(fg - o64, dn))
+                lo, hi = osc.leaf_box(pid, gpu[k, 2], gpu[k, 3])
+                if dist <= np.linalg.norm(hi - lo) + 1e-6 * (abs(gt[k]) + 1.0):
+                    kind = "tangent"
         if kind == "hard":
             # the side that hit: does the ray merely clip its leaf box?
             for side_hit, pid, u, v, t in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k], ora["t"][k]),
