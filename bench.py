@@ -6,10 +6,12 @@ Workload (default): 1,000,000 patches (2000 seeded displaced tori / apple tori,
 ray per pixel (cosine-weighted bounce from seeded surface points).  Synthetic,
 seeded, generated on the host and resident in HBM before timing starts.
 
-A step is one pass over all primary and all secondary rays.  Two variants are
-timed: "plain" (one launch per ray class, the library's default launch
-parameters) and "batched" (both classes as two batches of one launch, launch
-parameters from the autotuner); `value` is the batched one.  W warm-up steps,
+Patches are subdivided in their local frames (Sec. 3.4; --world-frames for world
+coordinates).  A step is one pass over all primary and all secondary rays.
+Variants: "plain" (one launch per ray class, default launch parameters),
+"batched" (both classes as two batches of one launch, autotuned), the same in
+world coordinates, and "learned_batched" (learned child order); `value` is the
+fastest batched variant that passes the oracle gate.  W warm-up steps,
 then K steps timed with HIP events recorded on the stream the kernels run on.
 Prints one JSON line.  The CPU baseline times the FP64 oracle on a bounded seeded
 sample of the same rays on the host cores and reports the parity of that sample.
@@ -106,6 +108,8 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batched variant with the given/default launch instead of the tuned one")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--world-frames", action="store_true",
+                    help="subdivide in world coordinates instead of patch-local frames (Sec. 3.4)")
     ap.add_argument("--policy-rays", type=int, default=1 << 20,
                     help="secondary rays on the 512-patch torus whose records train the ordering network")
     ap.add_argument("--policy-steps", type=int, default=4000, help="Adam steps of the ordering network")
@@ -143,7 +147,8 @@ def main():
     log(f"workload {w.name}: {w.cp.shape[0]} patches, {len(w.primary)} + {len(w.diffuse)} rays "
         f"(generated in {gen_s:.1f} s)")
     t0 = time.time()
-    scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
+    scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
+                      local_frames=not args.world_frames)
     torch.cuda.synchronize()
     create_s = time.time() - t0
     if args.launch:
@@ -225,6 +230,26 @@ def main():
                 and np.array_equal(hits_d.view(np.uint32), hd.cpu().numpy().view(np.uint32)))
         log(f"batched: {ms:.3f} ms/step -> {variants['batched']['mrays_per_s']:.1f} MRays/s "
             f"(launch {variants['batched']['launch']})")
+    if args.only == "" and not args.world_frames:
+        # the same launch with subdivision in world coordinates, for the Sec. 3.4 comparison
+        wsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
+        wsc.set_launch(**{k: v for k, v in scene.get_launch().items() if k != "waves_per_cu"})
+        wh = [torch.empty_like(hp), torch.empty_like(hd)]
+        wb = [(0, prim, wh[0]), (0, diff, wh[1])]
+
+        def world_step(evs=None):
+            if evs:
+                evs[0].record(stream)
+            wsc.intersect_batched(wb)
+            if evs:
+                evs[1].record(stream)
+
+        laps, ms = timed(world_step, 2)
+        variants["batched_world_frames"] = {
+            "ms_per_step": ms, "mrays_per_s": (n_p + n_d) / (ms * 1e-3) / 1e6, "launches_per_step": 1,
+            "kernel_ms": float(np.mean(laps)), "note": "closest-first, both classes in one launch, world frame"}
+        log(f"batched, world frame: {ms:.3f} ms/step -> {variants['batched_world_frames']['mrays_per_s']:.1f} MRays/s")
+        del wsc, wh, wb
     learned_hits = None
     if args.only in ("", "learned"):
         policy, pstats = train_policy(args, torch, ccs, scenes)
@@ -302,7 +327,7 @@ def main():
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
         threads = min(threads, os.cpu_count() or threads)
         t0 = time.time()
-        osc = oracle.Scene(w.cp, w.types, w.leaf_depth)
+        osc = oracle.Scene(w.cp, w.types, w.leaf_depth, local_frames=not args.world_frames)
         obuild = time.time() - t0
         calib = scenes.sample_indices(n_p, 1024, seed=91)
         t0 = time.time()
@@ -354,6 +379,7 @@ def main():
                                "learned_batched": "learned child order, both ray classes in one autotuned launch"
                                }[head],
                    "launch": variants[head]["launch"],
+                   "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
                    "leaf_depth": w.leaf_depth},
         "variants": variants,
         "roofline": roofline,
@@ -374,7 +400,8 @@ def train_policy(args, torch, ccs, scenes):
     c1 = scenes.config1()
     rays = scenes.policy_training_rays(args.policy_rays)
     gen_s = time.time() - t0
-    g1 = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+    g1 = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth,
+                   local_frames=not args.world_frames)
 
     def records(r_np):
         r = torch.from_numpy(r_np).cuda()
@@ -413,7 +440,8 @@ def bench_animation(args, torch, ccs, scenes):
     n_rays = sum(len(r) for r in a.rays)
     log(f"workload {a.name}: {a.cp0.shape[0]} patches, {nf} frames, {n_rays} rays "
         f"({[len(r) for r in a.rays]}), generated in {gen_s:.1f} s")
-    scene = ccs.Scene(torch.from_numpy(a.cp0).cuda(), torch.from_numpy(a.types).cuda(), a.leaf_depth)
+    scene = ccs.Scene(torch.from_numpy(a.cp0).cuda(), torch.from_numpy(a.types).cuda(), a.leaf_depth,
+                      local_frames=not args.world_frames)
     scene.set_frames(nf)
     cps = [torch.from_numpy(c).cuda() for c in a.frames]
     rays = [torch.from_numpy(r).cuda() for r in a.rays]
@@ -460,7 +488,7 @@ def bench_animation(args, torch, ccs, scenes):
         per_frame = 4096
         osec, ok, worst, nsamp = 0.0, True, 1.0, 0
         for f in range(nf):
-            osc = oracle.Scene(a.frames[f], a.types, a.leaf_depth)
+            osc = oracle.Scene(a.frames[f], a.types, a.leaf_depth, local_frames=not args.world_frames)
             sel = scenes.sample_indices(len(a.rays[f]), min(per_frame, len(a.rays[f])), seed=200 + f)
             t0 = time.time()
             o = osc.intersect(a.rays[f][sel], nthreads=threads)
@@ -480,6 +508,7 @@ def bench_animation(args, torch, ccs, scenes):
         "dtype": "f32", "data": "synthetic (seeded)",
         "config": {"workload": f"{a.name}: {a.cp0.shape[0]} patches, {nf} frames, {n_rays} rays "
                                f"(half primary, half secondary per frame)",
+                   "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
                    "launch": scene.get_launch(), "autotuned": tuned is not None, "leaf_depth": a.leaf_depth,
                    "ms_median": float(np.median(laps))},
         "roofline": None, "cpu_baseline": cpu, "parity_sample": parity, "source_hash": source_hash()}),
@@ -497,7 +526,8 @@ def bench_combined(args, torch, ccs, scenes):
     log(f"workload {w.name}: {w.cp.shape[0]} patches ({int(w.types.sum())} Gregory), {len(w.primary)} primary "
         f"rays, {w.n_frames} frames, {w.bounces} bounces; generated in {time.time() - t0:.1f} s")
     t0 = time.time()
-    scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
+    scene = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
+                      local_frames=not args.world_frames)
     scene.set_frames(w.n_frames)
     cps = []
     for f in range(w.n_frames):
@@ -575,7 +605,7 @@ def bench_combined(args, torch, ccs, scenes):
         parity, osec, nsamp = {}, 0.0, 0
         for j, f in enumerate((0, F - 1)):
             t0 = time.time()
-            osc = oracle.Scene(w.frame(f), w.types, w.leaf_depth)
+            osc = oracle.Scene(w.frame(f), w.types, w.leaf_depth, local_frames=not args.world_frames)
             log(f"oracle scene of frame {f} in {time.time() - t0:.1f} s")
             for b in range(B + 1):
                 r = samples[b][j]
@@ -597,6 +627,7 @@ def bench_combined(args, torch, ccs, scenes):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
         "config": {"workload": f"{w.name}: {w.cp.shape[0]} patches, {F} frames, {n} primary rays + {B} bounces "
                                f"per frame ({F * (B + 1) * n} rays per step)", "leaf_depth": w.leaf_depth,
+                   "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
                    "variant": "closest-first order, batched over frames"},
         "variants": variants, "roofline": None, "cpu_baseline": cpu, "parity_sample": parity,
         "device_memory_gib": {"scene_all_frames": round(info["device_bytes"] / 2**30, 3),

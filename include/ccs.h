@@ -47,6 +47,18 @@ extern "C" {
 
 #define CCS_NO_HIT 0xFFFFFFFFu
 #define CCS_MAX_LEAF_DEPTH 16
+/* Scene flag: subdivide every patch in its own frame (Sec. 3.4: boxes in patch-local
+ * frames overlap less, so fewer subdomains survive the slab tests).  The frame of a
+ * patch has rows r0 = unit(p30 - p00), r1 = unit of (p03 - p00) with its r0 part
+ * removed, r2 = r0 x r1 (the identity when the u or v edge is degenerate), computed
+ * in double and stored in fp32; patch points and each candidate ray are mapped by
+ * it, so ray parameters are unchanged and the subdivision boxes, including the leaf
+ * box whose entry distance is reported, are boxes in the patch's frame, each grown
+ * on all sides by 2^-19 of the patch's largest extent in that frame (corners and
+ * straight edges lie on box faces there, where rounding would open gaps between
+ * neighbours; Sec. 3.4 closes them by growing boxes).  The BVH stays in world
+ * space.  Frames follow the geometry on refit. */
+#define CCS_FLAG_LOCAL_FRAMES 1u
 
 typedef enum ccs_status {
   CCS_OK = 0,
@@ -83,7 +95,7 @@ typedef struct ccs_scene_desc {
   uint32_t n_patches;           /* 0 <= n < 2^31; an empty scene makes every ray miss */
   int32_t location;             /* CCS_HOST or CCS_DEVICE */
   uint32_t leaf_depth;          /* L, 1..16 */
-  uint32_t flags;               /* must be 0 */
+  uint32_t flags;               /* 0 or CCS_FLAG_LOCAL_FRAMES */
   void* stream;                 /* hipStream_t used for the uploads */
 } ccs_scene_desc;
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libccs.so")
 CCS_OK, CCS_ERR_INVALID_ARG, CCS_ERR_OOM, CCS_ERR_HIP, CCS_ERR_UNSUPPORTED = range(5)
 CCS_BEZIER, CCS_GREGORY = 0, 1
 CCS_HOST, CCS_DEVICE = 0, 1
+CCS_FLAG_LOCAL_FRAMES = 1
 NO_HIT = 0xFFFFFFFF
 COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
 
@@ -126,7 +127,7 @@ class Scene:
     patch_types: (n,) uint8 (0 Bezier, 1 Gregory); leaf_depth: L in [1, 16].
     """
 
-    def __init__(self, control_points, patch_types, leaf_depth: int, stream=None):
+    def __init__(self, control_points, patch_types, leaf_depth: int, stream=None, local_frames: bool = False):
         import torch
         cp = torch.as_tensor(control_points)
         ty = torch.as_tensor(patch_types)
@@ -141,8 +142,10 @@ class Scene:
             ty = ty.to(cp.device)
         self.n = int(cp.shape[0])
         self.leaf_depth = int(leaf_depth)
+        self.local_frames = bool(local_frames)
         desc = SceneDesc(cp.data_ptr() if self.n else None, ty.data_ptr() if self.n else None, self.n,
-                         CCS_DEVICE if on_dev else CCS_HOST, self.leaf_depth, 0,
+                         CCS_DEVICE if on_dev else CCS_HOST, self.leaf_depth,
+                         CCS_FLAG_LOCAL_FRAMES if local_frames else 0,
                          _stream(stream).value if on_dev else None)
         h = C.c_void_p()
         _check(lib().ccs_scene_create(C.byref(desc), C.byref(h)))

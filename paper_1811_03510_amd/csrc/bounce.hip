@@ -113,6 +113,14 @@ __global__ __launch_bounds__(kBounceBlock) void k_bounce(DeviceScene s, const cc
   float nx = fu[1] * fv[2] - fu[2] * fv[1];
   float ny = fu[2] * fv[0] - fu[0] * fv[2];
   float nz = fu[0] * fv[1] - fu[1] * fv[0];
+  if (s.frames) {  // record in the patch's frame: the normal back to world space (rows transposed)
+    const float4 r0 = s.frames[3 * (size_t)rec_idx], r1 = s.frames[3 * (size_t)rec_idx + 1],
+                 r2 = s.frames[3 * (size_t)rec_idx + 2];
+    const float lx = nx, ly = ny, lz = nz;
+    nx = r0.x * lx + r1.x * ly + r2.x * lz;
+    ny = r0.y * lx + r1.y * ly + r2.y * lz;
+    nz = r0.z * lx + r1.z * ly + r2.z * lz;
+  }
   const float inv_len = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
   nx *= inv_len;
   ny *= inv_len;
@@ -122,7 +130,7 @@ __global__ __launch_bounds__(kBounceBlock) void k_bounce(DeviceScene s, const cc
     ny = -ny;
     nz = -nz;
   }
-  // leaf domain containing (u, v)
+  // leaf domain containing (u, v); its box is taken in the frame the patch is subdivided in
   const uint32_t leaf = (1u << 23) >> s.leaf_depth;
   const uint32_t pu = min((uint32_t)floorf(h.u * 8388608.0f) & ~(leaf - 1u), (1u << 23) - leaf);
   const uint32_t pv = min((uint32_t)floorf(h.v * 8388608.0f) & ~(leaf - 1u), (1u << 23) - leaf);
@@ -136,7 +144,8 @@ __global__ __launch_bounds__(kBounceBlock) void k_bounce(DeviceScene s, const cc
       lo[1] = fminf(lo[1], qy[a][b]); hi[1] = fmaxf(hi[1], qy[a][b]);
       lo[2] = fminf(lo[2], qz[a][b]); hi[2] = fmaxf(hi[2], qz[a][b]);
     }
-  const float off = (hi[0] + dx - lo[0]) + (hi[1] + dy - lo[1]) + (hi[2] + dz - lo[2]);
+  float off = (hi[0] + dx - lo[0]) + (hi[1] + dy - lo[1]) + (hi[2] + dz - lo[2]);
+  if (s.frames) off += 6.0f * s.frames[3 * (size_t)rec_idx].w;  // the box pad on both sides of 3 axes
   o.ox = fmaf(off, nx, fmaf(h.t, r.dx, r.ox));
   o.oy = fmaf(off, ny, fmaf(h.t, r.dy, r.oy));
   o.oz = fmaf(off, nz, fmaf(h.t, r.dz, r.oz));

@@ -187,7 +187,7 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
     return fail(CCS_ERR_INVALID_ARG, "leaf_depth must be in [1, 16]");
   if (desc->location != CCS_HOST && desc->location != CCS_DEVICE)
     return fail(CCS_ERR_INVALID_ARG, "location must be CCS_HOST or CCS_DEVICE");
-  if (desc->flags != 0) return fail(CCS_ERR_UNSUPPORTED, "flags must be 0");
+  if ((desc->flags & ~CCS_FLAG_LOCAL_FRAMES) != 0) return fail(CCS_ERR_UNSUPPORTED, "unknown flags");
 
   // host-side validation needs no GPU; device input is fetched first
   std::vector<float> cp;
@@ -340,6 +340,24 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
   D.n_frames = 1;
   D.frame_rec_floats = (size_t)n * ccs::kRecFloats;
   D.frame_node_f4 = (size_t)n_nodes * 4;
+  if ((desc->flags & CCS_FLAG_LOCAL_FRAMES) && n > 0) {
+    // frames, and records in them, come from the refit kernel, so that creation and
+    // every later refit compute them with the same arithmetic
+    D.frame_frames_f4 = (size_t)n * 3;
+    if ((st = dev_alloc(s, &D.frames, D.frame_frames_f4)) != CCS_OK) {
+      free_scene(s);
+      return st;
+    }
+    st = ccs_refit_frame(s, 0, cp.data(), CCS_HOST, desc->stream);
+    if (st == CCS_OK) {
+      e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) st = hip_fail(e, "placing patches in their frames");
+    }
+    if (st != CCS_OK) {
+      free_scene(s);
+      return st;
+    }
+  }
   *out = s;
   return CCS_OK;
 }
@@ -354,11 +372,17 @@ ccs_status ccs_scene_set_frames(ccs_scene* s, uint32_t n_frames) {
   if (e != hipSuccess) return hip_fail(e, "synchronizing before re-allocating frames");
   float* recs = nullptr;
   float4* nodes = nullptr;
+  float4* frames = nullptr;
   ccs_status st = dev_alloc(s, &recs, D.frame_rec_floats * n_frames);
-  if (st != CCS_OK) return st;
-  st = dev_alloc(s, &nodes, D.frame_node_f4 * n_frames);
+  if (st == CCS_OK) st = dev_alloc(s, &nodes, D.frame_node_f4 * n_frames);
+  if (st == CCS_OK && D.frames) st = dev_alloc(s, &frames, D.frame_frames_f4 * n_frames);
+  auto drop_new = [&]() {
+    if (recs) dev_free(s, recs, D.frame_rec_floats * n_frames * sizeof(float));
+    if (nodes) dev_free(s, nodes, D.frame_node_f4 * n_frames * sizeof(float4));
+    if (frames) dev_free(s, frames, D.frame_frames_f4 * n_frames * sizeof(float4));
+  };
   if (st != CCS_OK) {
-    dev_free(s, recs, D.frame_rec_floats * n_frames * sizeof(float));
+    drop_new();
     return st;
   }
   // every frame starts as a copy of frame 0
@@ -367,16 +391,20 @@ ccs_status ccs_scene_set_frames(ccs_scene* s, uint32_t n_frames) {
       e = hipMemcpy(recs + f * D.frame_rec_floats, D.recs, D.frame_rec_floats * sizeof(float), hipMemcpyDeviceToDevice);
     if (e == hipSuccess && D.frame_node_f4)
       e = hipMemcpy(nodes + f * D.frame_node_f4, D.nodes, D.frame_node_f4 * sizeof(float4), hipMemcpyDeviceToDevice);
+    if (e == hipSuccess && frames)
+      e = hipMemcpy(frames + f * D.frame_frames_f4, D.frames, D.frame_frames_f4 * sizeof(float4),
+                    hipMemcpyDeviceToDevice);
   }
   if (e != hipSuccess) {
-    dev_free(s, recs, D.frame_rec_floats * n_frames * sizeof(float));
-    dev_free(s, nodes, D.frame_node_f4 * n_frames * sizeof(float4));
+    drop_new();
     return hip_fail(e, "copying frame 0");
   }
   dev_free(s, D.recs, D.frame_rec_floats * D.n_frames * sizeof(float));
   dev_free(s, const_cast<float4*>(D.nodes), D.frame_node_f4 * D.n_frames * sizeof(float4));
+  if (D.frames) dev_free(s, D.frames, D.frame_frames_f4 * D.n_frames * sizeof(float4));
   D.recs = recs;
   D.nodes = nodes;
+  D.frames = frames;
   D.n_frames = n_frames;
   return CCS_OK;
 }
@@ -410,6 +438,7 @@ ccs_status ccs_refit_frame(ccs_scene* s, uint32_t frame, const float* control_po
   ccs::DeviceScene f = s->dev;
   f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
   f.nodes = s->dev.nodes + frame * s->dev.frame_node_f4;
+  if (f.frames) f.frames = s->dev.frames + frame * s->dev.frame_frames_f4;
   hipError_t e = ccs::launch_refit(f, src, s->level_offsets.data(), (uint32_t)s->level_offsets.size() - 1, st);
   if (e != hipSuccess) return hip_fail(e, "refit launch");
   return CCS_OK;
@@ -513,6 +542,7 @@ ccs_status ccs_bounce_frame(const ccs_scene* s, uint32_t frame, const ccs_ray* r
   ccs::DeviceScene f = s->dev;
   f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
   f.nodes = s->dev.nodes + frame * s->dev.frame_node_f4;
+  if (f.frames) f.frames = s->dev.frames + frame * s->dev.frame_frames_f4;
   hipError_t e = ccs::launch_bounce(f, rays, hits, uniforms, n, out_rays, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "bounce launch");
   return CCS_OK;

@@ -38,6 +38,9 @@ struct DeviceScene {
   size_t frame_rec_floats;   // floats per frame in recs (n_patches * kRecFloats)
   size_t frame_node_f4;      // float4s per frame in nodes (n_nodes * 4)
   PolicyDev policy;          // set: learned child ordering (see policy.h); w == nullptr: closest first
+  float4* frames;            // patch-local frames: 3 rows per record (per frame), row 0's w = the box pad;
+                             // nullptr: world frame
+  size_t frame_frames_f4;    // float4s per frame in frames (n_patches * 3)
 };
 
 // Rays of one launch: up to kMaxBatches batches, each with its own frame, ray

@@ -136,6 +136,29 @@ __device__ __forceinline__ void patch_frame(float4 anchor, float ox, float oy, f
   ptmin = (float)((double)tmin - (double)t0);
 }
 
+// Patch frame of a ray in a patch-local frame (rows r0, r1, r2): the anchored
+// origin of patch_frame and the direction are mapped by the rows in double and
+// rounded once, so that the mapped ray is as exact as the stored mapped patch
+// (rounding a mapped direction twice would tilt it, and a grazing ray would then
+// meet the surface leaves away).
+__device__ __forceinline__ void patch_frame_rows(float4 anchor, float4 r0, float4 r1, float4 r2, float ox, float oy,
+                                                 float oz, float dx, float dy, float dz, float tmin, float& pox,
+                                                 float& poy, float& poz, float& pdx, float& pdy, float& pdz,
+                                                 float& ptmin, float& t0) {
+  const float qx = anchor.x - ox, qy = anchor.y - oy, qz = anchor.z - oz;
+  t0 = (qx * dx + qy * dy + qz * dz) * __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
+  const double ax = fma((double)t0, (double)dx, (double)ox - (double)anchor.x);
+  const double ay = fma((double)t0, (double)dy, (double)oy - (double)anchor.y);
+  const double az = fma((double)t0, (double)dz, (double)oz - (double)anchor.z);
+  pox = (float)((double)r0.x * ax + (double)r0.y * ay + (double)r0.z * az);
+  poy = (float)((double)r1.x * ax + (double)r1.y * ay + (double)r1.z * az);
+  poz = (float)((double)r2.x * ax + (double)r2.y * ay + (double)r2.z * az);
+  pdx = (float)((double)r0.x * dx + (double)r0.y * dy + (double)r0.z * dz);
+  pdy = (float)((double)r1.x * dx + (double)r1.y * dy + (double)r1.z * dz);
+  pdz = (float)((double)r2.x * dx + (double)r2.y * dy + (double)r2.z * dz);
+  ptmin = (float)((double)tmin - (double)t0);
+}
+
 // Closed slab test on [tmin, cap]; returns the entry distance or +inf when missed.
 __device__ __forceinline__ float slab(const RayP& r, float lx, float ly, float lz, float hx, float hy, float hz,
                                       float cap) {

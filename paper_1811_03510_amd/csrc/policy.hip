@@ -36,7 +36,17 @@ __global__ __launch_bounds__(64) void k_record(DeviceScene s, const ccs_ray* __r
     const float4 meta = reinterpret_cast<const float4*>(rec)[15];
     const bool greg = (__float_as_uint(meta.w) & kGregoryBit) != 0;
     float pox, poy, poz, ptmin, pt0;  // pt0 unused: no cap here
-    patch_frame(meta, ro.x, ro.y, ro.z, rd.x, rd.y, rd.z, ro.w, pox, poy, poz, ptmin, pt0);
+    float dxp = rd.x, dyp = rd.y, dzp = rd.z;  // direction in the frame the patch is subdivided in
+    if (!s.frames) patch_frame(meta, ro.x, ro.y, ro.z, rd.x, rd.y, rd.z, ro.w, pox, poy, poz, ptmin, pt0);
+    if (s.frames) {
+      const float4* fr = s.frames + 3 * (size_t)s.inv_perm[id];
+      const float4 r0 = fr[0], r1 = fr[1], r2 = fr[2];
+      patch_frame_rows(meta, r0, r1, r2, ro.x, ro.y, ro.z, rd.x, rd.y, rd.z, ro.w, pox, poy, poz, dxp, dyp, dzp,
+                       ptmin, pt0);
+      pox += r0.w;  // the box pad, as in the intersection kernel
+      poy += r0.w;
+      poz += r0.w;
+    }
     // the reported (u, v) is a leaf centre (2i + 1) 2^-(L+1): scaling by 2^L is exact
     const float scale = __uint_as_float((127u + L) << 23);
     const uint32_t iu = (uint32_t)(h.z * scale), iv = (uint32_t)(h.w * scale);
@@ -46,15 +56,23 @@ __global__ __launch_bounds__(64) void k_record(DeviceScene s, const ccs_ray* __r
     load_grid(rec, P, greg);
     float qx[4][4], qy[4][4], qz[4][4], dx, dy, dz;
     calc_points_and_d(P, greg, u0, u0 + size, v0, v0 + size, qx, qy, qz, dx, dy, dz);
+    if (s.frames) {
+      const float pad2 = 2.0f * s.frames[3 * (size_t)s.inv_perm[id]].w;
+      dx += pad2;
+      dy += pad2;
+      dz += pad2;
+    }
     Grid G;
     orient(qx, false, G.x);
     orient(qy, false, G.y);
     orient(qz, false, G.z);
     Row7 e[4];
     SlabPair sp = {ptmin, __builtin_inff(), ptmin, __builtin_inff()};
-    split_fold(G.x, pox, safe_inv(rd.x), dx, e, sp);
-    split_fold(G.y, poy, safe_inv(rd.y), dy, e, sp);
-    split_fold(G.z, poz, safe_inv(rd.z), dz, e, sp);
+    // reciprocals rounded back to a direction, exactly as the intersection kernel sees it
+    const float ix = safe_inv(dxp), iy = safe_inv(dyp), iz = safe_inv(dzp);
+    split_fold(G.x, pox, ix, dx, e, sp);
+    split_fold(G.y, poy, iy, dy, e, sp);
+    split_fold(G.z, poz, iz, dz, e, sp);
     // no cap: the reported hit lies on the boxes' boundary as often as not, and a
     // capped test there would turn on rounding
     const bool ha = sp.na <= sp.fa * kFarScale, hb = sp.nb <= sp.fb * kFarScale;
@@ -62,7 +80,9 @@ __global__ __launch_bounds__(64) void k_record(DeviceScene s, const ccs_ray* __r
       const float sx[4] = {qx[0][0], qx[3][0], qx[0][3], qx[3][3]};
       const float sy[4] = {qy[0][0], qy[3][0], qy[0][3], qy[3][3]};
       const float sz[4] = {qz[0][0], qz[3][0], qz[0][3], qz[3][3]};
-      policy_inputs(sx, sy, sz, 0u, pox, poy, poz, rd.x, rd.y, rd.z, sp, (int)(2 * k), (int)L, greg, f);
+      const float fdx = s.frames ? 1.0f / ix : rd.x, fdy = s.frames ? 1.0f / iy : rd.y,
+                  fdz = s.frames ? 1.0f / iz : rd.z;
+      policy_inputs(sx, sy, sz, 0u, pox, poy, poz, fdx, fdy, fdz, sp, (int)(2 * k), (int)L, greg, f);
       label = 2u * ((iu >> (L - 1 - k)) & 1u) + ((iv >> (L - 1 - k)) & 1u);
     }
   }

@@ -118,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
   uint32_t code = 0, trail = 0, mirror = 0;
   int depth = 0;
   uint32_t vpref = 0;  // learned order: bit 0 set = take the v-half in bit 1 at the next split
+  float pad2 = 0.0f;   // patch-local frames: twice the current patch's box pad (added to d)
 
   for (;;) {
     if (__ballot(mode != kDead) == 0) break;
@@ -191,8 +192,27 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
           const float* rec = recs + (size_t)rec_idx * kRecFloats;
           const float4 meta = reinterpret_cast<const float4*>(rec)[15];
           pmeta = __float_as_uint(meta.w);
-          patch_frame(meta, wr.ox, wr.oy, wr.oz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane], wr.tmin, pox, poy,
-                      poz, ptmin, pt0);
+          if (s.frames) {
+            // patch-local frame: origin and direction mapped by the patch's rows; the
+            // reciprocals hold the mapped direction until the lane leaves the patch
+            const float4* fr = s.frames + (size_t)bt.frame[batch_of(bt, rid)] * s.frame_frames_f4 + 3 * (size_t)rec_idx;
+            const float4 r0 = fr[0], r1 = fr[1], r2 = fr[2];
+            float pdx, pdy, pdz;
+            patch_frame_rows(meta, r0, r1, r2, wr.ox, wr.oy, wr.oz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane],
+                             wr.tmin, pox, poy, poz, pdx, pdy, pdz, ptmin, pt0);
+            wr.ix = safe_inv(pdx);
+            wr.iy = safe_inv(pdy);
+            wr.iz = safe_inv(pdz);
+            // boxes grown by the pad on all sides: the low planes move by -pad through the
+            // origin (o + pad), the high planes by +pad through d + 2 pad
+            pox += r0.w;
+            poy += r0.w;
+            poz += r0.w;
+            pad2 = 2.0f * r0.w;
+          } else {
+            patch_frame(meta, wr.ox, wr.oy, wr.oz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane], wr.tmin, pox,
+                        poy, poz, ptmin, pt0);
+          }
           code = trail = mirror = 0;
           depth = 0;
           if (pmeta & kGregoryBit) {
@@ -204,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
             orient(P.x, false, G.x);
             orient(P.y, false, G.y);
             orient(P.z, false, G.z);
-            dx = dy = dz = 0.0f;
+            dx = dy = dz = pad2;
             mode = kStep;
           }
           break;
@@ -252,6 +272,11 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
         load_grid(recs + (size_t)rec_idx * kRecFloats, P, greg);
         float qx[4][4], qy[4][4], qz[4][4];
         calc_points_and_d(P, greg, u0, u0 + su, v0, v0 + sv, qx, qy, qz, dx, dy, dz);
+        if (s.frames) {
+          dx += pad2;
+          dy += pad2;
+          dz += pad2;
+        }
         const bool along_v = (depth & 1) != 0;
         orient(qx, along_v, G.x);
         orient(qy, along_v, G.y);
@@ -367,8 +392,12 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
             sz[2] = second ? ocz[1] : G.z[3][0];
             sz[3] = second ? G.z[3][0] : ocz[1];
             float f[16];
-            policy_inputs(sx, sy, sz, mirror0, pox, poy, poz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane], sp2,
-                          depth - 1, s.leaf_depth, (pmeta & kGregoryBit) != 0, f);
+            // the direction in the frame the patch is subdivided in
+            const float fdx = s.frames ? 1.0f / wr.ix : s_dir[0][lane];
+            const float fdy = s.frames ? 1.0f / wr.iy : s_dir[1][lane];
+            const float fdz = s.frames ? 1.0f / wr.iz : s_dir[2][lane];
+            policy_inputs(sx, sy, sz, mirror0, pox, poy, poz, fdx, fdy, fdz, sp2, depth - 1, s.leaf_depth,
+                          (pmeta & kGregoryBit) != 0, f);
             policy_store_inputs(s_feat, lane, f);
             mode = kDecide;
           }
@@ -383,13 +412,20 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
           depth = L2 - b;
           mode = kGrid;
           if (kStats) cnt.backtrack++;
-        } else if (sp > 0) {  // patch done: next candidate from the stack
-          --sp;
-          cur = stack[sp * kBlock + lane];
-          mode = kTraverse;
-        } else {  // ray done
-          write_hit<kStats>(bt, counters, rid, best_t, best_id, s_uv[0][lane], s_uv[1][lane], cnt);
-          mode = kFetch;
+        } else {
+          if (s.frames) {  // patch done: world reciprocals back for the traversal
+            wr.ix = safe_inv(s_dir[0][lane]);
+            wr.iy = safe_inv(s_dir[1][lane]);
+            wr.iz = safe_inv(s_dir[2][lane]);
+          }
+          if (sp > 0) {  // next candidate from the stack
+            --sp;
+            cur = stack[sp * kBlock + lane];
+            mode = kTraverse;
+          } else {  // ray done
+            write_hit<kStats>(bt, counters, rid, best_t, best_id, s_uv[0][lane], s_uv[1][lane], cnt);
+            mode = kFetch;
+          }
         }
       }
     }

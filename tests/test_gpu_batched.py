@@ -22,10 +22,11 @@ def anim():
     return S.config3(n_frames=4, lo=1 << 10, hi=1 << 14)
 
 
-@pytest.fixture(scope="module")
-def scene(anim):
+@pytest.fixture(scope="module", params=["world", "local"])
+def scene(anim, request):
     from paper_1811_03510_amd import ccs
-    g = ccs.Scene(torch.from_numpy(anim.cp0).cuda(), torch.from_numpy(anim.types).cuda(), anim.leaf_depth)
+    g = ccs.Scene(torch.from_numpy(anim.cp0).cuda(), torch.from_numpy(anim.types).cuda(), anim.leaf_depth,
+                  local_frames=request.param == "local")
     g.set_frames(len(anim.frames))
     for f, cp in enumerate(anim.frames):
         g.refit_frame(f, torch.from_numpy(cp).cuda())
@@ -38,7 +39,7 @@ def test_frames_match_the_oracle(anim, scene):
         _say(f"frame {f}: {len(rays)} rays")
         (h,) = scene.intersect_batched([(f, torch.from_numpy(rays).cuda(), None)])
         torch.cuda.synchronize()
-        osc = O.Scene(cp, anim.types, anim.leaf_depth)
+        osc = O.Scene(cp, anim.types, anim.leaf_depth, local_frames=scene.local_frames)
         assert_gate(gate(h.cpu().numpy(), osc.intersect(rays), rays, osc, anim.diameter, anim.leaf_depth,
                          label=f"anim-frame{f}"))
 
@@ -160,7 +161,7 @@ def test_bounce_on_a_frame_uses_that_frames_geometry(anim, scene):
     hits[:, 0], hits[:, 2], hits[:, 3] = t, u, v
     hits[:, 1] = idx.astype(np.uint32).view(np.float32)
     w = rng.uniform(size=(n, 2)).astype(np.float32)
-    ref = O.Scene(cp, anim.types, L).bounce(rays, hits, w)
+    ref = O.Scene(cp, anim.types, L, local_frames=scene.local_frames).bounce(rays, hits, w)
     out = scene.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda(),
                        frame=f)
     out0 = scene.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda())

@@ -25,10 +25,23 @@ def ccs():
     return m
 
 
+@pytest.fixture(scope="module", params=["world", "local"])
+def frames(request):
+    """Subdivision in world coordinates, or in patch-local frames (Sec. 3.4)."""
+    return request.param == "local"
+
+
 @pytest.fixture(scope="module")
-def c1_gpu(ccs, c1):
-    _say("building the 512-patch torus scene on the GPU")
-    return ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+def c1_gpu(ccs, c1, frames):
+    _say(f"building the 512-patch torus scene on the GPU (local frames: {frames})")
+    return ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth,
+                     local_frames=frames)
+
+
+@pytest.fixture(scope="module")
+def c1_ref(c1, c1_oracle, frames):
+    """The oracle in the same frames as c1_gpu."""
+    return O.Scene(c1.cp, c1.types, c1.leaf_depth, local_frames=True) if frames else c1_oracle
 
 
 def run(scene, rays_np):
@@ -39,7 +52,8 @@ def run(scene, rays_np):
 
 
 @pytest.mark.parametrize("cls", ["primary", "diffuse"])
-def test_torus512_all_rays(ccs, c1, c1_oracle, c1_gpu, cls):
+def test_torus512_all_rays(ccs, c1, c1_ref, c1_gpu, cls):
+    c1_oracle = c1_ref
     rays = c1.primary if cls == "primary" else c1.diffuse
     _say(f"torus512 {cls}: {len(rays)} rays")
     g = run(c1_gpu, rays)
@@ -73,7 +87,8 @@ def test_launch_configuration_never_changes_results(ccs, c1, c1_gpu):
         c1_gpu.set_launch(0, 0, 16, 16)
 
 
-def test_counted_kernel_gives_the_same_hits(ccs, c1, c1_gpu, c1_oracle):
+def test_counted_kernel_gives_the_same_hits(ccs, c1, c1_gpu, c1_ref):
+    c1_oracle = c1_ref
     r = torch.from_numpy(c1.primary).cuda()
     h0 = c1_gpu.intersect(r)
     h1, cnt = c1_gpu.intersect_counted(r)
@@ -107,14 +122,14 @@ def affine_cp(rng):
 
 
 @pytest.mark.parametrize("L", [1, 4, 12, 16])
-def test_single_patches_and_special_rays(ccs, L):
+def test_single_patches_and_special_rays(ccs, L, frames):
     rng = np.random.default_rng(L)
     for trial in range(4):
         cp = affine_cp(rng) if trial < 2 else S.config1(8, 8, False).cp[rng.integers(0, 512)].astype(np.float64)
         cp = cp.astype(np.float32)[None]
         ty = np.array([trial % 2], np.uint8)
-        osc = O.Scene(cp, ty, L)
-        gsc = ccs.Scene(torch.from_numpy(cp).cuda(), torch.from_numpy(ty).cuda(), L)
+        osc = O.Scene(cp, ty, L, local_frames=frames)
+        gsc = ccs.Scene(torch.from_numpy(cp).cuda(), torch.from_numpy(ty).cuda(), L, local_frames=frames)
         x = S.surface_points(cp, ty, np.zeros(256, np.int64), rng.uniform(size=256), rng.uniform(size=256))
         d = rng.normal(size=(256, 3))
         rays = np.zeros((256 + 6, 8), np.float32)
@@ -162,7 +177,8 @@ def test_rays_through_shared_edges_never_miss(ccs, c1, c1_gpu):
     assert np.all(g[:, 0] <= t_target + 1e-4 * c1.diameter)
 
 
-def test_bounce_matches_oracle(ccs, c1, c1_oracle, c1_gpu):
+def test_bounce_matches_oracle(ccs, c1, c1_ref, c1_gpu):
+    c1_oracle = c1_ref
     """Secondary rays from the same (ray, hit, uniforms) inputs on both sides."""
     rng = np.random.default_rng(8)
     n = 4096
@@ -193,7 +209,7 @@ def test_bounce_matches_oracle(ccs, c1, c1_oracle, c1_gpu):
     np.testing.assert_allclose(out[active, 4:7], ref[active, 4:7], atol=2e-5)
 
 
-def test_refit_matches_oracle_on_moved_scene(ccs, c1):
+def test_refit_matches_oracle_on_moved_scene(ccs, c1, frames):
     """Moving the control points (a smooth displacement field: shared points move
     together) and refitting gives the oracle's hits on the moved scene; refitting
     back gives bitwise the original hits."""
@@ -202,12 +218,13 @@ def test_refit_matches_oracle_on_moved_scene(ccs, c1):
     k = np.array([[0.9, 0.3, 0.1], [0.2, -0.7, 0.5], [0.1, 0.4, -0.9]]) * 2 * np.pi
     disp = 0.01 * np.sin(x @ k.T + np.array([0.3, 1.1, 2.0]))
     cp1 = (x + disp).reshape(cp0.shape).astype(np.float32)
-    gsc = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+    gsc = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth,
+                    local_frames=frames)
     base = run(gsc, c1.primary)
     _say("refit to moved control points")
     gsc.refit(torch.from_numpy(cp1).cuda())
     g = run(gsc, c1.primary)
-    osc = O.Scene(cp1, c1.types, c1.leaf_depth)
+    osc = O.Scene(cp1, c1.types, c1.leaf_depth, local_frames=frames)
     o = osc.intersect(c1.primary)
     assert_gate(gate(g, o, c1.primary, osc, c1.diameter, c1.leaf_depth, label="torus512-refit"))
     gsc.refit(torch.from_numpy(c1.cp))  # host input
@@ -215,13 +232,14 @@ def test_refit_matches_oracle_on_moved_scene(ccs, c1):
     assert np.array_equal(back.view(np.uint32), base.view(np.uint32))
 
 
-def test_instanced_1m_full_size_sampled(ccs):
+def test_instanced_1m_full_size_sampled(ccs, frames):
     """1,000,000 patches, 1920x1080 primary + secondary rays in the launch the
     benchmark times; the oracle checks a seeded sample of each class."""
     _say("generating the 1M-patch scene")
     w = S.config2()
-    gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
-    osc = O.Scene(w.cp, w.types, w.leaf_depth)
+    gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
+                    local_frames=frames)
+    osc = O.Scene(w.cp, w.types, w.leaf_depth, local_frames=frames)
     for cls, rays in (("primary", w.primary), ("diffuse", w.diffuse)):
         _say(f"1M {cls}: {len(rays)} rays on the GPU")
         g = run(gsc, rays)
