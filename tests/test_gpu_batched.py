@@ -173,3 +173,56 @@ def test_bounce_on_a_frame_uses_that_frames_geometry(anim, scene):
     with pytest.raises(ccs.CcsError):
         scene.bounce(torch.from_numpy(rays).cuda(), torch.from_numpy(hits).cuda(), torch.from_numpy(w).cuda(),
                      frame=len(anim.frames))
+
+
+def test_graph_captured_refit_intersect_bounce_loop(anim, scene):
+    """[refit every frame -> one batched launch -> bounce rays on every frame ->
+    one batched launch of the bounces] captured once and replayed three times,
+    each replay bitwise equal to the eager loop; the bounce hits pass the oracle
+    gate on every frame."""
+    F = len(anim.frames)
+    cps = [torch.from_numpy(cp).cuda() for cp in anim.frames]
+    rays = [torch.from_numpy(r).cuda() for r in anim.rays]
+    hits = [torch.empty((r.shape[0], 4), dtype=torch.float32, device="cuda") for r in rays]
+    bray = [torch.empty_like(r) for r in rays]
+    bhit = [torch.empty_like(h) for h in hits]
+    rng = np.random.default_rng(8)
+    unif = [torch.from_numpy(rng.uniform(size=(r.shape[0], 2)).astype(np.float32)).cuda() for r in rays]
+
+    def loop():
+        for f in range(F):
+            scene.refit_frame(f, cps[f])
+        scene.intersect_batched([(f, rays[f], hits[f]) for f in range(F)])
+        for f in range(F):
+            scene.bounce(rays[f], hits[f], unif[f], out=bray[f], frame=f)
+        scene.intersect_batched([(f, bray[f], bhit[f]) for f in range(F)])
+
+    loop()
+    torch.cuda.synchronize()
+    eager = [h.cpu().numpy().copy() for h in bhit]
+    eager_rays = [r.cpu().numpy().copy() for r in bray]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        loop()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        loop()
+    for rep in range(3):
+        for h, r in zip(bhit, bray):
+            h.fill_(-1.0)
+            r.fill_(0.0)
+        (torch.randn(1 << 20, device="cuda") * 3).sum().item()  # eager work between replays
+        _say(f"bounce-loop graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        for e, er, h, r in zip(eager, eager_rays, bhit, bray):
+            assert np.array_equal(er.view(np.uint32), r.cpu().numpy().view(np.uint32))
+            assert np.array_equal(e.view(np.uint32), h.cpu().numpy().view(np.uint32))
+    for f in range(F):
+        osc = O.Scene(anim.frames[f], anim.types, anim.leaf_depth, local_frames=scene.local_frames)
+        r = eager_rays[f]
+        assert_gate(gate(eager[f], osc.intersect(r), r, osc, anim.diameter, anim.leaf_depth,
+                         label=f"bounce-frame{f}"))

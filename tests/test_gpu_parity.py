@@ -248,3 +248,21 @@ def test_instanced_1m_full_size_sampled(ccs, frames):
         rep = gate(g[sel], o, rays[sel], osc, w.diameter, w.leaf_depth, label=f"1M-{cls}-sample")
         assert_gate(rep, min_match=0.999)
         assert rep["oracle_hits"] > 500
+
+
+def test_instanced_1m_refit_to_an_animation_frame(ccs, frames):
+    """The 1M-patch scene refit to a frame of the seeded animation (every level of
+    its 27-deep BVH refit in its own launch) against the oracle on that frame."""
+    _say("generating the 1M-patch scene and an animation frame")
+    w = S.config2(with_diffuse=False)
+    cp1 = S.animate(w.cp, 5, 16)
+    gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
+                    local_frames=frames)
+    gsc.refit(torch.from_numpy(cp1).cuda())
+    sel = S.sample_indices(len(w.primary), 8192, seed=79)
+    rays = w.primary[sel]
+    g = run(gsc, rays)
+    osc = O.Scene(cp1, w.types, w.leaf_depth, local_frames=frames)
+    rep = gate(g, osc.intersect(rays), rays, osc, w.diameter, w.leaf_depth, label="1M-refit-frame5")
+    assert_gate(rep, min_match=0.999)
+    assert rep["oracle_hits"] > 1000
