@@ -1,0 +1,63 @@
+"""The autotuner's search and cache on the CPU, with a stand-in scene whose launch
+time is a known function of its parameters."""
+import json
+
+import pytest
+
+from paper_1811_03510_amd import autotune
+
+
+class FakeScene:
+    def __init__(self):
+        self.p = dict(autotune.DEFAULT)
+        self.calls = 0
+
+    def set_launch(self, **p):
+        self.p = dict(p)
+
+    def get_launch(self):
+        return dict(self.p)
+
+    def info(self):
+        return dict(n_patches=10, leaf_depth=4, n_frames=1)
+
+
+def fake_time(scene, batches, reps=3):
+    scene.calls += 1
+    p = scene.p
+    # minimum at fetch_min 24, grid_min 8, traverse_steps 3; everything else flat
+    return 1.0 + 0.01 * abs(p["fetch_min"] - 24) + 0.02 * abs(p["grid_min"] - 8) + 0.05 * abs(p["traverse_steps"] - 3)
+
+
+def test_coordinate_descent_finds_the_minimum(monkeypatch):
+    monkeypatch.setattr(autotune, "time_launch", fake_time)
+    sc = FakeScene()
+    best, ms, trials = autotune.tune(sc, [])
+    assert best["fetch_min"] == 24 and best["grid_min"] == 8 and best["traverse_steps"] == 3
+    assert ms == pytest.approx(1.0)
+    assert sc.p == best
+    assert "decide_min" not in {k for t, _ in trials for k in t if t[k] != autotune.DEFAULT[k]}
+    _, _, trials_l = autotune.tune(FakeScene(), [], learned=True)
+    assert any(t["decide_min"] != autotune.DEFAULT["decide_min"] for t, _ in trials_l)
+
+
+def test_results_are_cached_by_key(monkeypatch, tmp_path):
+    monkeypatch.setattr(autotune, "time_launch", fake_time)
+    monkeypatch.setattr(autotune, "workload_key", lambda scene, batches: "w1")
+    monkeypatch.setenv("CCS_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+
+    class Props:
+        gcnArchName = "gfx950:sramecc+:xnack-"
+    torch = pytest.importorskip("torch")
+    monkeypatch.setattr(torch.cuda, "current_device", lambda: 0)
+    monkeypatch.setattr(torch.cuda, "get_device_properties", lambda i: Props())
+    sc = FakeScene()
+    p = autotune.tuned(sc, [], name="x")
+    first = sc.calls
+    assert first > 5
+    cache = json.loads((tmp_path / "cache.json").read_text())
+    assert len(cache) == 1 and next(iter(cache.values()))["params"] == p
+    sc2 = FakeScene()
+    assert autotune.tuned(sc2, [], name="x") == p and sc2.calls == 0 and sc2.p == p
+    autotune.tuned(sc2, [], name="y")  # another workload name: tuned again
+    assert sc2.calls > 0 and len(json.loads((tmp_path / "cache.json").read_text())) == 2

@@ -274,3 +274,22 @@ def test_trained_network_against_closest_first(ccs, c1, c1_gpu, c1_oracle):
          f"re-crops/ray {cp[:, 6].mean():.3f} vs {cl[:, 6].mean():.3f}")
     o = c1_oracle.intersect(rays)
     assert_gate(gate(hl.cpu().numpy(), o, rays, c1_oracle, c1.diameter, c1.leaf_depth, label="learned-trained"))
+
+
+def test_learned_order_in_local_frames_passes_the_gate(ccs, c1):
+    """Learned order on a scene subdivided in patch-local frames: records, training
+    and traversal in that frame; hits against the oracle in the same frame."""
+    g = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth,
+                  local_frames=True)
+    osc = O.Scene(c1.cp, c1.types, c1.leaf_depth, local_frames=True)
+    tr = _dev(S.policy_training_rays(1 << 15))
+    f, y = g.record(tr, g.intersect(tr))
+    keep = (y != 255).nonzero().squeeze(1)
+    f, y = f[keep].contiguous(), y[keep].contiguous()
+    th = _dev(S.mlp_init())
+    ccs.policy_train(th, f, y, steps=300, batch=2048, lr=3e-3, seed=2, bf16=True)
+    rays = np.concatenate([c1.primary, c1.diffuse])
+    g.set_policy(th)
+    h = g.intersect(_dev(rays)).cpu().numpy()
+    g.set_policy(None)
+    assert_gate(gate(h, osc.intersect(rays), rays, osc, c1.diameter, c1.leaf_depth, label="learned-local"))
