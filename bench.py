@@ -250,6 +250,37 @@ def main():
             "kernel_ms": float(np.mean(laps)), "note": "closest-first, both classes in one launch, world frame"}
         log(f"batched, world frame: {ms:.3f} ms/step -> {variants['batched_world_frames']['mrays_per_s']:.1f} MRays/s")
         del wsc, wh, wb
+    bounce = None
+    if args.only == "":
+        # secondary rays as the 1M configuration states them: one cosine bounce per primary
+        # hit, generated on the GPU from that launch's hits (seeded uniforms); rays of
+        # missed pixels are inactive and are not counted
+        u = torch.from_numpy(scenes.uniform(scenes.substream(scenes.STREAM_BOUNCE, 7), 2 * n_p)
+                             .astype(np.float32)).cuda()
+        hit_rows = (hbp[:, 0] < float("inf")).nonzero().squeeze(1)
+        brays = scene.bounce(prim[hit_rows].contiguous(), hbp[hit_rows].contiguous(), u[:2 * hit_rows.numel()]
+                             .reshape(-1, 2).contiguous())
+        bh = torch.empty((brays.shape[0], 4), dtype=torch.float32, device="cuda")
+        hp2 = torch.empty_like(hp)
+        bb = [(0, prim, hp2), (0, brays, bh)]
+
+        def bounce_step(evs=None):
+            if evs:
+                evs[0].record(stream)
+            scene.intersect_batched(bb)
+            if evs:
+                evs[1].record(stream)
+
+        laps, ms = timed(bounce_step, 2)
+        nb = brays.shape[0]
+        variants["batched_bounce"] = {
+            "ms_per_step": ms, "mrays_per_s": (n_p + nb) / (ms * 1e-3) / 1e6, "launches_per_step": 1,
+            "kernel_ms": float(np.mean(laps)), "rays": {"primary": n_p, "bounce": nb},
+            "bounce_hit_fraction": float((bh[:, 0] < float("inf")).float().mean().item()) if nb else 0.0,
+            "note": "closest-first, primary rays plus one GPU-generated bounce per primary hit, one launch"}
+        bounce = (brays.cpu().numpy(), bh.cpu().numpy())
+        log(f"batched with real bounces ({nb} bounce rays): {ms:.3f} ms/step -> "
+            f"{variants['batched_bounce']['mrays_per_s']:.1f} MRays/s")
     learned_hits = None
     if args.only in ("", "learned"):
         policy, pstats = train_policy(args, torch, ccs, scenes)
@@ -342,12 +373,19 @@ def main():
         od = osc.intersect(w.diffuse[sel_d], nthreads=threads)
         osec = time.time() - t0
         cpu = {"value": round(2 * k / osec / 1e6, 4), "unit": "MRays/s", "cores": threads, "kind": "oracle",
+               "per_core": round(2 * k / osec / 1e6 / threads, 5), "cpu_model": cpu_model(),
                "sample": f"{k} primary + {k} secondary rays (seeded subset of the same {n_p}+{n_d} rays), "
                          f"{osec:.1f} s; oracle BVH build {obuild:.1f} s excluded"}
         rp = gate(hits_p[sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="primary")
         rd = gate(hits_d[sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="diffuse")
         parity = {c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
                       "excused": r["excused"], "ok": r["ok"]} for c, r in (("primary", rp), ("diffuse", rd))}
+        if bounce is not None:
+            sel_b = scenes.sample_indices(len(bounce[0]), min(len(bounce[0]), 65536), seed=94)
+            ob = osc.intersect(bounce[0][sel_b], nthreads=threads)
+            rb = gate(bounce[1][sel_b], ob, bounce[0][sel_b], osc, w.diameter, w.leaf_depth, label="bounce")
+            variants["batched_bounce"]["parity_sample"] = {"rays": rb["n"], "same_hit_and_patch": rb["id_rate"],
+                                                           "excused": rb["excused"], "ok": rb["ok"]}
         if learned_hits is not None:
             lp_ = gate(learned_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="l-primary")
             ld_ = gate(learned_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="l-diffuse")
@@ -391,6 +429,16 @@ def main():
         "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def train_policy(args, torch, ccs, scenes):
