@@ -63,7 +63,7 @@ extern "C" {
 typedef enum ccs_status {
   CCS_OK = 0,
   CCS_ERR_INVALID_ARG = 1, /* null pointer, bad tag, L out of range, non-finite input, size mismatch */
-  CCS_ERR_OOM = 2,         /* device or host allocation failed */
+  CCS_ERR_OOM = 2,         /* device or host allocation failed, or refused by CCS_MAX_DEVICE_BYTES */
   CCS_ERR_HIP = 3,         /* a HIP runtime call failed; see ccs_last_error() */
   CCS_ERR_UNSUPPORTED = 4  /* no gfx950 device, or a flag this build does not support */
 } ccs_status;
@@ -284,15 +284,40 @@ typedef struct ccs_train_params {
   uint32_t reserved;
 } ccs_train_params;
 
+/* Adam's moments and step count, for training in several calls: m and v are
+ * caller-owned device arrays of CCS_POLICY_PARAMS floats, t the number of steps
+ * already taken with them (all zero for a fresh start; at most 2^32). */
+typedef struct ccs_adam_state {
+  float* m;
+  float* v;
+  uint64_t t;
+} ccs_adam_state;
+
 /* Trains params (device, CCS_POLICY_PARAMS fp32, updated in place) with Adam
  * on the rows (features n x 16, labels n) for tp->steps minibatches.
+ * state: NULL to start from zero moments at step 0 (moments then live in
+ * temporaries), else read and updated in place, t advanced by tp->steps; step
+ * t + s of a resumed call draws the minibatch and bias corrections that global
+ * step t + s draws in one uninterrupted call, so k steps followed by j resumed
+ * steps give the bits of k + j steps at once (same n, tp except steps).
  * loss_history: NULL or device array of tp->steps floats receiving each step's
  * minibatch loss before its update.  Deterministic for a given seed.
  * Synchronous. */
 ccs_status ccs_policy_train(float* params, const float* features, const uint8_t* labels, uint32_t n,
-                            const ccs_train_params* tp, float* loss_history, void* stream);
+                            const ccs_train_params* tp, ccs_adam_state* state, float* loss_history, void* stream);
 
 ccs_status ccs_scene_info_get(const ccs_scene* scene, ccs_scene_info* info);
+
+/* Device memory cap.  Every device allocation of the library (scene buffers,
+ * animation frames, packed network operands, the temporaries of the synchronous
+ * policy calls) is refused with CCS_ERR_OOM when it would bring the bytes the
+ * library holds in this process above the value of the environment variable
+ * CCS_MAX_DEVICE_BYTES (a decimal byte count, read at each allocation; unset,
+ * empty or 0: no cap; anything else: CCS_ERR_INVALID_ARG).  A call that fails
+ * this way frees whatever it had allocated.  ccs_device_bytes_in_use() returns
+ * the bytes held right now: the sum of ccs_scene_info.device_bytes over live
+ * scenes plus the temporaries of calls in progress.  Thread-safe. */
+uint64_t ccs_device_bytes_in_use(void);
 
 /* Frees every device buffer of the scene (synchronizes the device first).  NULL is a no-op. */
 void ccs_scene_destroy(ccs_scene* scene);

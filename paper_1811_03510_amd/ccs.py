@@ -26,7 +26,7 @@ EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_coun
            "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
            "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched",
            "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train",
-           "ccs_bounce_frame")
+           "ccs_bounce_frame", "ccs_device_bytes_in_use")
 MAX_BATCHES = 32
 POLICY_PARAMS = 1732
 NO_LABEL = 255
@@ -65,6 +65,10 @@ class TrainParams(C.Structure):
                 ("reserved", C.c_uint32)]
 
 
+class AdamState(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("v", C.c_void_p), ("t", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -96,10 +100,12 @@ def lib():
         L.ccs_policy_record.argtypes = [vp, vp, vp, u32, vp, vp, vp]
         L.ccs_policy_infer.argtypes = [vp, vp, u32, vp, vp]
         L.ccs_policy_grad.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
-        L.ccs_policy_train.argtypes = [vp, vp, vp, u32, C.POINTER(TrainParams), vp, vp]
+        L.ccs_policy_train.argtypes = [vp, vp, vp, u32, C.POINTER(TrainParams), C.POINTER(AdamState), vp, vp]
+        L.ccs_device_bytes_in_use.argtypes = []
         for name in EXPORTS:
-            if name not in ("ccs_scene_destroy", "ccs_last_error"):
+            if name not in ("ccs_scene_destroy", "ccs_last_error", "ccs_device_bytes_in_use"):
                 getattr(L, name).restype = C.c_int
+        L.ccs_device_bytes_in_use.restype = C.c_uint64
         _lib = L
     return _lib
 
@@ -322,9 +328,22 @@ def policy_grad(params, features, labels, bf16: bool = False, stream=None):
     return float(loss.item()), g
 
 
+class Adam:
+    """Adam's moments (two CUDA float32 tensors of 1732 values) and its step count,
+    carried across policy_train calls."""
+
+    def __init__(self, device="cuda", m=None, v=None, t: int = 0):
+        import torch
+        self.m = torch.zeros(POLICY_PARAMS, dtype=torch.float32, device=device) if m is None else _params(m)
+        self.v = torch.zeros(POLICY_PARAMS, dtype=torch.float32, device=device) if v is None else _params(v)
+        self.t = int(t)
+
+
 def policy_train(params, features, labels, steps: int, batch: int = 4096, lr: float = 3e-3, beta1: float = 0.9,
-                 beta2: float = 0.999, eps: float = 1e-8, seed: int = 0, bf16: bool = True, stream=None):
-    """Adam on the ordering network, params updated in place; returns the per-step loss."""
+                 beta2: float = 0.999, eps: float = 1e-8, seed: int = 0, bf16: bool = True, state: Adam = None,
+                 stream=None):
+    """Adam on the ordering network, params updated in place; returns the per-step loss.
+    state: None for a fresh start, else an Adam whose moments and step count are used and advanced."""
     import torch
     p, f = _params(params), _rows(features, 16, torch.float32)
     y = _rows(labels, 0, torch.uint8)
@@ -332,8 +351,19 @@ def policy_train(params, features, labels, steps: int, batch: int = 4096, lr: fl
         raise ValueError("one label per row")
     hist = torch.empty(max(1, steps), dtype=torch.float32, device=f.device)
     tp = TrainParams(steps, batch, lr, beta1, beta2, eps, seed, int(bf16), 0)
-    _check(lib().ccs_policy_train(_ptr(p), _ptr(f), _ptr(y), f.shape[0], C.byref(tp), _ptr(hist), _stream(stream)))
+    st = None
+    if state is not None:
+        st = AdamState(_ptr(_params(state.m)), _ptr(_params(state.v)), state.t)
+    _check(lib().ccs_policy_train(_ptr(p), _ptr(f), _ptr(y), f.shape[0], C.byref(tp),
+                                  C.byref(st) if st is not None else None, _ptr(hist), _stream(stream)))
+    if st is not None:
+        state.t = int(st.t)
     return hist[:steps]
+
+
+def device_bytes_in_use() -> int:
+    """Device bytes the library holds in this process (every scene and call temporaries)."""
+    return int(lib().ccs_device_bytes_in_use())
 
 
 def hit_ids(hits) -> np.ndarray:

@@ -5,8 +5,11 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cerrno>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <utility>
 #include <string>
 #include <thread>
 #include <vector>
@@ -32,6 +35,51 @@ ccs_status hip_fail(hipError_t e, const char* what) {
 constexpr int kTraversalStack = (int)ccs::kMaxBvhDepth;  // the LDS node stack of the intersect kernel
 constexpr uint32_t kQueueSlots = 256;  // ray-queue counters, one per launch in flight on a scene
 
+// Device bytes held by the library (every scene and every call's temporaries).
+std::atomic<uint64_t> g_live_bytes{0};
+
+// The cap from CCS_MAX_DEVICE_BYTES, read on every allocation; 0 means none.
+ccs_status device_cap(uint64_t& cap) {
+  cap = 0;
+  const char* v = std::getenv("CCS_MAX_DEVICE_BYTES");
+  if (!v || !*v) return CCS_OK;
+  char* end = nullptr;
+  errno = 0;
+  const unsigned long long c = std::strtoull(v, &end, 10);
+  if (errno != 0 || *end != '\0' || v[0] == '-')
+    return fail(CCS_ERR_INVALID_ARG, std::string("CCS_MAX_DEVICE_BYTES is not a byte count: ") + v);
+  cap = (uint64_t)c;
+  return CCS_OK;
+}
+
+// Every device allocation of the library goes through this pair.
+ccs_status raw_alloc(void** q, size_t bytes) {
+  *q = nullptr;
+  uint64_t cap;
+  ccs_status st = device_cap(cap);
+  if (st != CCS_OK) return st;
+  const uint64_t before = g_live_bytes.fetch_add(bytes);
+  if (cap != 0 && before + bytes > cap) {
+    g_live_bytes.fetch_sub(bytes);
+    return fail(CCS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes would exceed " +
+                                 "CCS_MAX_DEVICE_BYTES=" + std::to_string(cap) + " (" + std::to_string(before) +
+                                 " bytes held)");
+  }
+  if (hipMalloc(q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    g_live_bytes.fetch_sub(bytes);
+    *q = nullptr;
+    return fail(CCS_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return CCS_OK;
+}
+
+void raw_free(void* q, size_t bytes) {
+  if (!q) return;
+  (void)hipFree(q);
+  g_live_bytes.fetch_sub(bytes);
+}
+
 }  // namespace
 
 struct ccs_scene {
@@ -48,7 +96,7 @@ struct ccs_scene {
   ccs_launch_params launch{0, 16, 1, 16, 2, 8};
   uint2* policy_w = nullptr;   // packed network fragments, allocated on first use
   float4* policy_b = nullptr;
-  std::vector<void*> allocations;
+  std::vector<std::pair<void*, size_t>> allocations;  // device buffers and their sizes
 };
 
 namespace {
@@ -56,32 +104,29 @@ namespace {
 template <class T>
 ccs_status dev_alloc(ccs_scene* s, T** p, size_t count) {
   *p = nullptr;
-  if (count == 0) count = 1;
+  const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(CCS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
-  s->allocations.push_back(q);
-  s->device_bytes += count * sizeof(T);
+  ccs_status st = raw_alloc(&q, bytes);
+  if (st != CCS_OK) return st;
+  s->allocations.emplace_back(q, bytes);
+  s->device_bytes += bytes;
   *p = static_cast<T*>(q);
   return CCS_OK;
 }
 
-void dev_free(ccs_scene* s, void* p, size_t bytes) {
+void dev_free(ccs_scene* s, void* p) {
   for (size_t k = 0; k < s->allocations.size(); ++k)
-    if (s->allocations[k] == p) {
-      (void)hipFree(p);
+    if (s->allocations[k].first == p) {
+      raw_free(p, s->allocations[k].second);
+      s->device_bytes -= s->allocations[k].second;
       s->allocations.erase(s->allocations.begin() + (long)k);
-      s->device_bytes -= bytes;
       return;
     }
 }
 
 void free_scene(ccs_scene* s) {
   if (!s) return;
-  for (void* p : s->allocations) (void)hipFree(p);
+  for (const auto& a : s->allocations) raw_free(a.first, a.second);
   delete s;
 }
 
@@ -120,19 +165,18 @@ namespace {
 
 // Device scratch owned by one synchronous call, freed on every return path.
 struct Scratch {
-  std::vector<void*> p;
+  std::vector<std::pair<void*, size_t>> p;
   ~Scratch() {
-    for (void* q : p) (void)hipFree(q);
+    for (const auto& q : p) raw_free(q.first, q.second);
   }
   template <class T>
   ccs_status alloc(T** out, size_t count) {
+    const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
     void* q = nullptr;
-    if (hipMalloc(&q, std::max<size_t>(1, count) * sizeof(T)) != hipSuccess) {
-      (void)hipGetLastError();
-      *out = nullptr;
-      return fail(CCS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
-    p.push_back(q);
+    *out = nullptr;
+    ccs_status st = raw_alloc(&q, bytes);
+    if (st != CCS_OK) return st;
+    p.emplace_back(q, bytes);
     *out = static_cast<T*>(q);
     return CCS_OK;
   }
@@ -377,9 +421,9 @@ ccs_status ccs_scene_set_frames(ccs_scene* s, uint32_t n_frames) {
   if (st == CCS_OK) st = dev_alloc(s, &nodes, D.frame_node_f4 * n_frames);
   if (st == CCS_OK && D.frames) st = dev_alloc(s, &frames, D.frame_frames_f4 * n_frames);
   auto drop_new = [&]() {
-    if (recs) dev_free(s, recs, D.frame_rec_floats * n_frames * sizeof(float));
-    if (nodes) dev_free(s, nodes, D.frame_node_f4 * n_frames * sizeof(float4));
-    if (frames) dev_free(s, frames, D.frame_frames_f4 * n_frames * sizeof(float4));
+    if (recs) dev_free(s, recs);
+    if (nodes) dev_free(s, nodes);
+    if (frames) dev_free(s, frames);
   };
   if (st != CCS_OK) {
     drop_new();
@@ -399,9 +443,9 @@ ccs_status ccs_scene_set_frames(ccs_scene* s, uint32_t n_frames) {
     drop_new();
     return hip_fail(e, "copying frame 0");
   }
-  dev_free(s, D.recs, D.frame_rec_floats * D.n_frames * sizeof(float));
-  dev_free(s, const_cast<float4*>(D.nodes), D.frame_node_f4 * D.n_frames * sizeof(float4));
-  if (D.frames) dev_free(s, D.frames, D.frame_frames_f4 * D.n_frames * sizeof(float4));
+  dev_free(s, D.recs);
+  dev_free(s, const_cast<float4*>(D.nodes));
+  if (D.frames) dev_free(s, D.frames);
   D.recs = recs;
   D.nodes = nodes;
   D.frames = frames;
@@ -632,48 +676,63 @@ ccs_status ccs_policy_grad(const float* params, const float* features, const uin
 }
 
 ccs_status ccs_policy_train(float* params, const float* features, const uint8_t* labels, uint32_t n,
-                            const ccs_train_params* tp, float* loss_history, void* stream) {
+                            const ccs_train_params* tp, ccs_adam_state* state, float* loss_history, void* stream) {
   g_error.clear();
   if (!params || !tp || (n > 0 && (!features || !labels))) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if (state && (!state->m || !state->v)) return fail(CCS_ERR_INVALID_ARG, "Adam state moments are NULL");
   if (n == 0 || tp->steps == 0) return CCS_OK;
   if (tp->batch == 0) return fail(CCS_ERR_INVALID_ARG, "batch is 0");
   if (!(tp->lr > 0.0f) || !(tp->beta1 >= 0.0f && tp->beta1 < 1.0f) || !(tp->beta2 >= 0.0f && tp->beta2 < 1.0f) ||
       !(tp->eps > 0.0f))
     return fail(CCS_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+  const uint64_t t0 = state ? state->t : 0;
+  if (t0 > (1ull << 32)) return fail(CCS_ERR_INVALID_ARG, "Adam step count above 2^32");
   const uint32_t batch = std::min(tp->batch, n);
   const uint32_t nblk = (batch + 63) / 64;
   const uint32_t per_epoch = std::max<uint32_t>(1, n / batch);
   hipStream_t str = (hipStream_t)stream;
   Scratch sc;
-  float *partial = nullptr, *lossp = nullptr, *m = nullptr, *v = nullptr;
+  float *partial = nullptr, *lossp = nullptr, *m = state ? state->m : nullptr, *v = state ? state->v : nullptr;
   ccs_status st = sc.alloc(&partial, (size_t)nblk * ccs::kPolicyParams);
   if (st == CCS_OK) st = sc.alloc(&lossp, (size_t)2 * nblk);
-  if (st == CCS_OK) st = sc.alloc(&m, (size_t)ccs::kPolicyParams);
-  if (st == CCS_OK) st = sc.alloc(&v, (size_t)ccs::kPolicyParams);
+  if (st == CCS_OK && !state) st = sc.alloc(&m, (size_t)ccs::kPolicyParams);
+  if (st == CCS_OK && !state) st = sc.alloc(&v, (size_t)ccs::kPolicyParams);
   if (st != CCS_OK) return st;
-  hipError_t e = ccs::launch_fill(m, ccs::kPolicyParams, 0.0f, str);
-  if (e == hipSuccess) e = ccs::launch_fill(v, ccs::kPolicyParams, 0.0f, str);
+  hipError_t e = hipSuccess;
+  if (!state) {
+    e = ccs::launch_fill(m, ccs::kPolicyParams, 0.0f, str);
+    if (e == hipSuccess) e = ccs::launch_fill(v, ccs::kPolicyParams, 0.0f, str);
+  }
+  // beta^t by the same sequence of double products an uninterrupted run forms
   double b1t = 1.0, b2t = 1.0;
+  for (uint64_t k = 0; k < t0 && (b1t != 0.0 || b2t != 0.0); ++k) {  // both stay 0 once they reach it
+    b1t *= tp->beta1;
+    b2t *= tp->beta2;
+  }
   uint64_t pa = 1, pc = 0, cur_epoch = ~0ull;
-  for (uint32_t step = 0; step < tp->steps && e == hipSuccess; ++step) {
+  for (uint32_t s = 0; s < tp->steps && e == hipSuccess; ++s) {
+    const uint64_t step = t0 + s;
     const uint64_t epoch = step / per_epoch;
     if (epoch != cur_epoch) {
       epoch_permutation(tp->seed, epoch, n, pa, pc);
       cur_epoch = epoch;
     }
-    const uint64_t pos0 = (uint64_t)(step % per_epoch) * batch;
+    const uint64_t pos0 = (step % per_epoch) * batch;
     e = ccs::launch_mlp_grad(params, features, labels, n, batch, pos0, pa, pc, tp->bf16 != 0, partial, lossp, str);
     b1t *= tp->beta1;
     b2t *= tp->beta2;
     if (e == hipSuccess)
       e = ccs::launch_mlp_adam(params, m, v, partial, lossp, nblk, tp->lr, tp->beta1, tp->beta2, tp->eps,
                                (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)),
-                               loss_history ? loss_history + step : nullptr, str);
+                               loss_history ? loss_history + s : nullptr, str);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(str);
   if (e != hipSuccess) return hip_fail(e, "policy training");
+  if (state) state->t = t0 + tp->steps;
   return CCS_OK;
 }
+
+uint64_t ccs_device_bytes_in_use(void) { return g_live_bytes.load(); }
 
 ccs_status ccs_scene_info_get(const ccs_scene* s, ccs_scene_info* info) {
   g_error.clear();

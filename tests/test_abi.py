@@ -110,16 +110,16 @@ def test_policy_and_batch_entry_points_validate_on_the_host():
     assert L.ccs_policy_grad(None, fake, fake, 4, 0, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_policy_grad(fake, None, fake, 4, 0, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
     tp = ccs.TrainParams(10, 0, 1e-3, 0.9, 0.999, 1e-8, 1, 1, 0)
-    assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None, None) == ccs.CCS_ERR_INVALID_ARG
     assert "batch" in L.ccs_last_error().decode()
     for bad in (dict(lr=0.0), dict(beta1=1.0), dict(beta2=-0.1), dict(eps=0.0)):
         kw = dict(steps=10, batch=64, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=1, bf16=1, reserved=0)
         kw.update(bad)
         tp = ccs.TrainParams(**kw)
-        assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None) == ccs.CCS_ERR_INVALID_ARG, bad
+        assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None, None) == ccs.CCS_ERR_INVALID_ARG, bad
     tp = ccs.TrainParams(0, 64, 1e-3, 0.9, 0.999, 1e-8, 1, 1, 0)
-    assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None) == ccs.CCS_OK  # no steps
-    assert L.ccs_policy_train(None, fake, fake, 100, C.byref(tp), None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_policy_train(fake, fake, fake, 100, C.byref(tp), None, None, None) == ccs.CCS_OK  # no steps
+    assert L.ccs_policy_train(None, fake, fake, 100, C.byref(tp), None, None, None) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_intersect_batched(None, None, 1, None) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_bounce_frame(None, 0, fake, fake, fake, 4, fake, None) == ccs.CCS_ERR_INVALID_ARG
     assert L.ccs_scene_set_frames(None, 2) == ccs.CCS_ERR_INVALID_ARG

@@ -156,6 +156,49 @@ def test_first_training_step_is_one_adam_update(ccs):
     assert np.allclose(got[big], want[big], rtol=0, atol=2e-6)
 
 
+def test_second_step_carries_adams_moments(ccs):
+    # step 1 from a fresh state, then step 2 resumed from the returned state: the
+    # moments must follow the reference update from the state of step 1
+    th0 = _params(6)
+    X, y = _records(512, 6)
+    th = _dev(th0.copy())
+    adam = ccs.Adam()
+    ccs.policy_train(th, _dev(X), _dev(y), steps=1, batch=512, lr=1e-3, seed=0, bf16=False, state=adam)
+    assert adam.t == 1
+    th1, m1, v1 = (a.cpu().numpy().astype(np.float64) for a in (th, adam.m, adam.v))
+    ccs.policy_train(th, _dev(X), _dev(y), steps=1, batch=512, lr=1e-3, seed=0, bf16=False, state=adam)
+    assert adam.t == 2
+    _, g = M.loss_and_grad(th1, X, y)
+    want, wm, wv = M.adam_step(th1, m1, v1, g, 2, 1e-3)
+    big = np.abs(g) > 1e-3
+    assert big.sum() > 100
+    assert np.allclose(adam.m.cpu().numpy()[big], wm[big], rtol=1e-4, atol=0)
+    assert np.allclose(adam.v.cpu().numpy()[big], wv[big], rtol=2e-4, atol=0)
+    assert np.allclose(th.cpu().numpy()[big], want[big], rtol=0, atol=2e-6)
+
+
+def test_training_resumes_bit_exactly_from_a_checkpoint(ccs, tmp_path):
+    from paper_1811_03510_amd import checkpoint
+    rng = np.random.default_rng(8)
+    X = rng.uniform(-1, 1, (20000, 16)).astype(np.float32)
+    y = (2 * (X[:, 1] > X[:, 2]) + (X[:, 7] > 0)).astype(np.uint8)
+    kw = dict(batch=1024, lr=3e-3, seed=5, bf16=True)  # 19 steps an epoch: the cut falls inside the second
+    th_a = _dev(S.mlp_init())
+    hist_a = ccs.policy_train(th_a, _dev(X), _dev(y), steps=50, **kw).cpu().numpy()
+    th_b = _dev(S.mlp_init())
+    adam = ccs.Adam()
+    h1 = ccs.policy_train(th_b, _dev(X), _dev(y), steps=23, state=adam, **kw).cpu().numpy()
+    path = str(tmp_path / "policy.npz")
+    checkpoint.save_training(path, th_b, adam, hyper=kw)
+    del th_b, adam
+    th_c, adam_c, hyper = checkpoint.load_training(path)
+    assert adam_c.t == 23 and hyper == kw
+    h2 = ccs.policy_train(th_c, _dev(X), _dev(y), steps=27, state=adam_c, **hyper).cpu().numpy()
+    assert adam_c.t == 50
+    assert np.array_equal(np.concatenate([h1, h2]).view(np.uint32), hist_a.view(np.uint32))
+    assert np.array_equal(th_c.cpu().numpy().view(np.uint32), th_a.cpu().numpy().view(np.uint32))
+
+
 def test_records_match_the_reference(ccs, c1, c1_gpu):
     rays = c1.diffuse[:3000]
     r = _dev(rays)
