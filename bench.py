@@ -55,11 +55,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# What the intersection kernel's machine code is built from: its source, the headers
+# it includes, and the build script that holds its compiler flags.
+KERNEL_SOURCES = ("paper_1811_03510_amd/csrc/trace.hip", "paper_1811_03510_amd/csrc/patch_math.h",
+                  "paper_1811_03510_amd/csrc/ccs_internal.h", "paper_1811_03510_amd/csrc/policy.h",
+                  "include/ccs.h", "paper_1811_03510_amd/build.py")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1811_03510_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
@@ -85,6 +91,46 @@ def traffic_from_profiles(kernel_ms_avg: float):
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def _counter_means(csv_dir: str, counter: str) -> dict:
+    """Mean value of `counter` per kernel name over the dispatches in a rocprofv3
+    --pmc CSV folder, and the largest single reading per kernel name."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: (sum(v) / len(v), max(v)) for k, v in vals.items()}
+
+
+def write_traffic_record(fetch_dir: str, write_dir: str, calib_mib: int) -> dict:
+    """profiles/intersect_traffic.json from a FETCH_SIZE and a WRITE_SIZE pass of
+    `bench.py --only batched ... --copy-calibration calib_mib`: the intersection
+    kernel's mean readings (KiB per dispatch), each scaled by known bytes over what
+    the same counter reads for the calibration's copy (FETCH) and fill (WRITE)."""
+    fetch, write = _counter_means(fetch_dir, "FETCH_SIZE"), _counter_means(write_dir, "WRITE_SIZE")
+    kib = calib_mib * 1024.0
+
+    def pick(d, key):
+        hits = [v for k, v in d.items() if key in k]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel matching {key!r}, found {sorted(d)}")
+        return hits[0]
+    k_fetch, k_write = pick(fetch, "k_trace<false, false>")[0], pick(write, "k_trace<false, false>")[0]
+    fetch_scale = kib / pick(fetch, "copyBuffer")[1]
+    write_scale = kib / pick(write, "elementwise")[1]
+    rec = {"source_hash": source_hash(), "kernel": "k_trace<false, false>",
+           "workload": "instanced1m batched, patch-local frames (2073600 + 2073600 rays)",
+           "fetch_kib": round(k_fetch, 1), "write_kib": round(k_write, 1),
+           "fetch_scale": round(fetch_scale, 3), "write_scale": round(write_scale, 3),
+           "bytes_per_launch": int(round((k_fetch * fetch_scale + k_write * write_scale) * 1024))}
+    with open(os.path.join(ROOT, "profiles", "intersect_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    return rec
 
 
 def main():
@@ -116,7 +162,15 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer once (a plain copy kernel of known size that "
                          "scales the profiler's FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no benchmark: write profiles/intersect_traffic.json from the rocprofv3 CSV folders of a "
+                         "FETCH_SIZE and a WRITE_SIZE pass run with --copy-calibration (its MIB is required)")
     args = ap.parse_args()
+    if args.write_traffic:
+        if not args.copy_calibration:
+            raise SystemExit("--write-traffic needs the --copy-calibration MIB the passes ran with")
+        print(json.dumps(write_traffic_record(*args.write_traffic, args.copy_calibration)))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

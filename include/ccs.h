@@ -250,7 +250,7 @@ ccs_status ccs_bounce_frame(const ccs_scene* scene, uint32_t frame, const ccs_ra
  * scene: later ccs_intersect* calls use the learned order.  NULL detaches it
  * (closest-first order).  The weights are packed on `stream`; params may be
  * freed once the stream has passed the call.  CCS_ERR_UNSUPPORTED when the
- * scene's BVH is deeper than 37 levels (the learned kernel's node stack). */
+ * scene's BVH is deeper than 31 levels (the learned kernel's node stack). */
 ccs_status ccs_scene_set_policy(ccs_scene* scene, const float* params, void* stream);
 
 /* Training records for n rays and their hits on frame 0 (device pointers).

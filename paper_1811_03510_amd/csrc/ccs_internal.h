@@ -62,10 +62,13 @@ struct LaunchParams {
   uint32_t* queue;
 };
 
-// BVH depth the learned variant's node stack holds (its LDS also holds the
-// policy's inputs); the closest-first variant holds kMaxBvhDepth.
+// BVH depth the learned variant's node stack holds (its LDS also holds a 64-byte
+// decision slot per lane; with 32 levels a wave's LDS stays within 1/12 of the
+// CU's, so 12 waves fit as in the closest-first variant, which holds
+// kMaxBvhDepth).  SAH builds of the 1M- and 8M-patch benchmark scenes are 27 and
+// 29 levels deep.
 constexpr uint32_t kMaxBvhDepth = 48;
-constexpr uint32_t kMaxBvhDepthLearned = 38;
+constexpr uint32_t kMaxBvhDepthLearned = 32;
 
 int max_waves_per_cu(bool counted, bool learned);
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,

@@ -54,19 +54,56 @@ __device__ __forceinline__ bf16x4 as_bf16x4(uint2 v) {
   return r;
 }
 
-// Inputs of a node at even depth, from its grid's corner points in storage
-// order (first, second index) = (0,0), (3,0), (0,3), (3,3) (the first index runs
-// along u; mirror bit 0 / 1: u / v stored reversed), a ray with origin o and
-// direction d in the patch frame, and the raw (uncapped) slab entries and exits
-// of the two u-halves in storage order.
-__device__ __forceinline__ void policy_inputs(const float sx[4], const float sy[4], const float sz[4],
-                                              uint32_t mirror, float ox, float oy, float oz, float dx, float dy,
-                                              float dz, const SlabPair& sp, int depth, int leaf_depth, bool gregory,
-                                              float f[16]) {
+// The per-node values the inputs are formed from (PolicyRaw): the node grid's
+// corner points in canonical (u, v) order (u0,v0), (u1,v0), (u0,v1), (u1,v1),
+// and the raw (uncapped) slab entry and exit of the lower and the upper u-half.
+struct PolicyRaw {
+  float cx[4], cy[4], cz[4];
+  float n_lo, n_up, x_lo, x_up;
+};
+
+// PolicyRaw of a node at even depth from its corners in storage order (first,
+// second index) = (0,0), (3,0), (0,3), (3,3) (the first index runs along u;
+// mirror bit 0 / 1: u / v stored reversed) and the slab results of the two
+// u-halves in storage order.
+__device__ __forceinline__ PolicyRaw policy_raw(const float sx[4], const float sy[4], const float sz[4],
+                                                uint32_t mirror, const SlabPair& sp) {
   const bool mu = (mirror & 1u) != 0, mv = (mirror & 2u) != 0;
-  const float n_lo = mu ? sp.nb : sp.na, n_up = mu ? sp.na : sp.nb;
-  const float x_lo = mu ? sp.fb : sp.fa, x_up = mu ? sp.fa : sp.fb;
-  const float t_in = fminf(n_lo, n_up);
+  PolicyRaw r;
+  r.n_lo = mu ? sp.nb : sp.na;
+  r.n_up = mu ? sp.na : sp.nb;
+  r.x_lo = mu ? sp.fb : sp.fa;
+  r.x_up = mu ? sp.fa : sp.fb;
+  // storage order to canonical (u, v) order by selects (no indexing by a run-time value)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r.cx[k] = sx[k];
+    r.cy[k] = sy[k];
+    r.cz[k] = sz[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k += 2) {  // u reversed: swap (0,1) and (2,3)
+    float t;
+    t = r.cx[k]; r.cx[k] = mu ? r.cx[k + 1] : t; r.cx[k + 1] = mu ? t : r.cx[k + 1];
+    t = r.cy[k]; r.cy[k] = mu ? r.cy[k + 1] : t; r.cy[k + 1] = mu ? t : r.cy[k + 1];
+    t = r.cz[k]; r.cz[k] = mu ? r.cz[k + 1] : t; r.cz[k + 1] = mu ? t : r.cz[k + 1];
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {  // v reversed: swap (0,2) and (1,3)
+    float t;
+    t = r.cx[k]; r.cx[k] = mv ? r.cx[k + 2] : t; r.cx[k + 2] = mv ? t : r.cx[k + 2];
+    t = r.cy[k]; r.cy[k] = mv ? r.cy[k + 2] : t; r.cy[k + 2] = mv ? t : r.cy[k + 2];
+    t = r.cz[k]; r.cz[k] = mv ? r.cz[k + 2] : t; r.cz[k + 2] = mv ? t : r.cz[k + 2];
+  }
+  return r;
+}
+
+// The 16 inputs from PolicyRaw, a ray with origin o and direction d in the patch
+// frame, the node's depth and the patch type.
+__device__ __forceinline__ void policy_features(const PolicyRaw& r, float ox, float oy, float oz, float dx,
+                                                float dy, float dz, int depth, int leaf_depth, bool gregory,
+                                                float f[16]) {
+  const float t_in = fminf(r.n_lo, r.n_up);
   const float dl = __fsqrt_rn(dx * dx + dy * dy + dz * dz);
   const float il = 1.0f / dl;
   const float nx = dx * il, ny = dy * il, nz = dz * il;
@@ -77,28 +114,10 @@ __device__ __forceinline__ void policy_inputs(const float sx[4], const float sy[
   const float e1x = 1.0f + sg * nx * nx * a, e1y = sg * b, e1z = -sg * nx;
   const float e2x = b, e2y = sg + ny * ny * a, e2z = -ny;
   const float px = ox + t_in * dx, py = oy + t_in * dy, pz = oz + t_in * dz;
-  // storage order to canonical (u, v) order by selects (no indexing by a run-time value)
-  float cx[4] = {sx[0], sx[1], sx[2], sx[3]};
-  float cy[4] = {sy[0], sy[1], sy[2], sy[3]};
-  float cz[4] = {sz[0], sz[1], sz[2], sz[3]};
-#pragma unroll
-  for (int k = 0; k < 4; k += 2) {  // u reversed: swap (0,1) and (2,3)
-    float t;
-    t = cx[k]; cx[k] = mu ? cx[k + 1] : t; cx[k + 1] = mu ? t : cx[k + 1];
-    t = cy[k]; cy[k] = mu ? cy[k + 1] : t; cy[k + 1] = mu ? t : cy[k + 1];
-    t = cz[k]; cz[k] = mu ? cz[k + 1] : t; cz[k + 1] = mu ? t : cz[k + 1];
-  }
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {  // v reversed: swap (0,2) and (1,3)
-    float t;
-    t = cx[k]; cx[k] = mv ? cx[k + 2] : t; cx[k + 2] = mv ? t : cx[k + 2];
-    t = cy[k]; cy[k] = mv ? cy[k + 2] : t; cy[k + 2] = mv ? t : cy[k + 2];
-    t = cz[k]; cz[k] = mv ? cz[k + 2] : t; cz[k + 2] = mv ? t : cz[k + 2];
-  }
   float s = 0.0f;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const float qx = cx[k] - px, qy = cy[k] - py, qz = cz[k] - pz;
+    const float qx = r.cx[k] - px, qy = r.cy[k] - py, qz = r.cz[k] - pz;
     f[3 * k + 0] = qx * e1x + qy * e1y + qz * e1z;
     f[3 * k + 1] = qx * e2x + qy * e2y + qz * e2z;
     f[3 * k + 2] = qx * nx + qy * ny + qz * nz;
@@ -109,10 +128,29 @@ __device__ __forceinline__ void policy_inputs(const float sx[4], const float sy[
 #pragma unroll
   for (int k = 0; k < 12; ++k) f[k] *= is;
   const float sc = dl * is;
-  f[12] = fminf(fmaxf((n_lo - n_up) * sc, -4.0f), 4.0f) * 0.25f;
-  f[13] = fminf(fmaxf((x_lo - x_up) * sc, -4.0f), 4.0f) * 0.25f;
+  f[12] = fminf(fmaxf((r.n_lo - r.n_up) * sc, -4.0f), 4.0f) * 0.25f;
+  f[13] = fminf(fmaxf((r.x_lo - r.x_up) * sc, -4.0f), 4.0f) * 0.25f;
   f[14] = (float)depth / (float)(2 * leaf_depth);
   f[15] = gregory ? 1.0f : 0.0f;
+}
+
+// The values policy_raw takes (corners and slab results in storage order)
+// through a lane's 64-byte slot of LDS: the intersection kernel keeps them there
+// between the split that meets a decision and the decision itself.
+__device__ __forceinline__ void policy_store_node(uint32_t* slots, int lane, const float sx[4], const float sy[4],
+                                                  const float sz[4], const SlabPair& sp) {
+  float4* o = reinterpret_cast<float4*>(slots + lane * 16);
+  o[0] = make_float4(sx[0], sx[1], sx[2], sx[3]);
+  o[1] = make_float4(sy[0], sy[1], sy[2], sy[3]);
+  o[2] = make_float4(sz[0], sz[1], sz[2], sz[3]);
+  o[3] = make_float4(sp.na, sp.fa, sp.nb, sp.fb);
+}
+__device__ __forceinline__ PolicyRaw policy_load_node(const uint32_t* slots, int lane, uint32_t mirror) {
+  const float4* i = reinterpret_cast<const float4*>(slots + lane * 16);
+  const float4 a = i[0], b = i[1], c = i[2], d = i[3];
+  const float sx[4] = {a.x, a.y, a.z, a.w}, sy[4] = {b.x, b.y, b.z, b.w}, sz[4] = {c.x, c.y, c.z, c.w};
+  const SlabPair sp = {d.x, d.y, d.z, d.w};
+  return policy_raw(sx, sy, sz, mirror, sp);
 }
 
 // One 16-sample column tile of the network on the matrix cores, computed
@@ -152,25 +190,29 @@ __device__ __forceinline__ f32x4 policy_tile(const PolicyDev& P, bf16x4 x, int l
   return z;
 }
 
-// A lane's 16 inputs as bfloat16 pairs into its 32-byte slot of `feat`.
+// A lane's 16 inputs as bfloat16 pairs into the first 32 bytes of its slot of
+// `feat` (kSlot words per slot).
+template <int kSlot>
 __device__ __forceinline__ void policy_store_inputs(uint32_t* feat, int lane, const float f[16]) {
-  uint4* o = reinterpret_cast<uint4*>(feat + lane * 8);
+  uint4* o = reinterpret_cast<uint4*>(feat + lane * kSlot);
   o[0] = make_uint4(bf16_pair(f[0], f[1]), bf16_pair(f[2], f[3]), bf16_pair(f[4], f[5]), bf16_pair(f[6], f[7]));
   o[1] = make_uint4(bf16_pair(f[8], f[9]), bf16_pair(f[10], f[11]), bf16_pair(f[12], f[13]),
                     bf16_pair(f[14], f[15]));
 }
 
 // The network for every lane whose bit is set in `need`: lane s's inputs are
-// read from its slot of `feat` (LDS, 64 slots of 8 words) and its four logits
-// are written back to the first 16 bytes of the slot.  Column tiles without a
-// requesting lane are skipped.  Must be executed by the whole wave.
+// read from its slot of `feat` (LDS, 64 slots of kSlot >= 8 words) and its four
+// logits are written back to the first 16 bytes of the slot.  Column tiles
+// without a requesting lane are skipped.  Must be executed by the whole wave.
+template <int kSlot>
 __device__ __forceinline__ void policy_wave(const PolicyDev& P, uint32_t* feat, uint64_t need, int lane) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (((need >> (16 * c)) & 0xFFFFull) == 0) continue;
-    const uint2 xv = reinterpret_cast<const uint2*>(feat)[(16 * c + (lane & 15)) * 4 + (lane >> 4)];
+    const uint2 xv = *reinterpret_cast<const uint2*>(feat + (16 * c + (lane & 15)) * kSlot + 2 * (lane >> 4));
     const f32x4 z = policy_tile(P, as_bf16x4(xv), lane);
-    if (lane < 16) reinterpret_cast<float4*>(feat)[(16 * c + lane) * 2] = make_float4(z[0], z[1], z[2], z[3]);
+    if (lane < 16)
+      *reinterpret_cast<float4*>(feat + (16 * c + lane) * kSlot) = make_float4(z[0], z[1], z[2], z[3]);
   }
 }
 

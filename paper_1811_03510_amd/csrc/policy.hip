@@ -82,7 +82,7 @@ __global__ __launch_bounds__(64) void k_record(DeviceScene s, const ccs_ray* __r
       const float sz[4] = {qz[0][0], qz[3][0], qz[0][3], qz[3][3]};
       const float fdx = s.frames ? 1.0f / ix : rd.x, fdy = s.frames ? 1.0f / iy : rd.y,
                   fdz = s.frames ? 1.0f / iz : rd.z;
-      policy_inputs(sx, sy, sz, 0u, pox, poy, poz, fdx, fdy, fdz, sp, (int)(2 * k), (int)L, greg, f);
+      policy_features(policy_raw(sx, sy, sz, 0u, sp), pox, poy, poz, fdx, fdy, fdz, (int)(2 * k), (int)L, greg, f);
       label = 2u * ((iu >> (L - 1 - k)) & 1u) + ((iv >> (L - 1 - k)) & 1u);
     }
   }
@@ -115,8 +115,8 @@ __global__ __launch_bounds__(64) void k_policy_infer(PolicyDev P, const float* _
 #pragma unroll
     for (int q = 0; q < 16; ++q) f[q] = 0.0f;
   }
-  policy_store_inputs(feat, lane, f);
-  policy_wave(P, feat, __ballot(in), lane);
+  policy_store_inputs<8>(feat, lane, f);
+  policy_wave<8>(P, feat, __ballot(in), lane);
   if (in) {
     const float4 lg = reinterpret_cast<const float4*>(feat)[2 * lane];
     reinterpret_cast<float4*>(z)[row] = lg;

@@ -51,11 +51,11 @@ __global__ __launch_bounds__(kRefitBlock) void k_refit_patches(DeviceScene s, co
   float lo[3] = {p[0], p[1], p[2]}, hi[3] = {p[0], p[1], p[2]};
 #pragma unroll
   for (int sl = 1; sl < 20; ++sl) {
-    if (sl >= 16 && !greg) break;
+    const bool in = sl < 16 || greg;  // a Bezier patch's hull is that of its 16 points
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], p[3 * sl + a]);
-      hi[a] = fmaxf(hi[a], p[3 * sl + a]);
+      lo[a] = in ? fminf(lo[a], p[3 * sl + a]) : lo[a];
+      hi[a] = in ? fmaxf(hi[a], p[3 * sl + a]) : hi[a];
     }
   }
   const float anc[3] = {meta.x, meta.y, meta.z};

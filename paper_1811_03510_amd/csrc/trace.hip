@@ -88,12 +88,19 @@ __device__ __forceinline__ void write_hit(const BatchTable& bt, uint32_t* __rest
 // closest-first half becomes the pending sibling) and has its grid recomputed;
 // one split later it takes the v-half of the network's top grandchild when both
 // v-halves are hit.
+// Three waves per SIMD (at most 168 VGPRs): the closest-first variant fits by
+// itself; the learned variant is held to it (a few loop-invariant values of the
+// ray-fetch and leaf-record paths then live in scratch instead of registers).
 template <bool kStats, bool kLearned>
-__global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
                                                   LaunchParams lp) {
   constexpr int kStack = kLearned ? (int)kMaxBvhDepthLearned : (int)kMaxBvhDepth;
   __shared__ int stack[kStack * kBlock];
-  __shared__ __align__(16) uint32_t s_feat[kLearned ? 64 * 8 : 4];  // policy inputs, then logits, per lane
+  // learned order, 16 words per lane: the node's corners and slab results from the
+  // split until the decision, then the network's inputs, then its logits; and the
+  // node's mirror bits
+  __shared__ __align__(16) uint32_t s_feat[kLearned ? 64 * 16 : 4];
+  __shared__ uint8_t s_mirror[kLearned ? 64 : 4];
   __shared__ float s_dir[3][kBlock];  // world direction: read only when a candidate is set up
   __shared__ float s_uv[2][kBlock];   // (u, v) of the best hit: written only by leaf records
   const int lane = threadIdx.x;
@@ -296,9 +303,20 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
     if (kLearned) {
       const uint64_t md = __ballot(mode == kDecide);
       if (md != 0 && ((uint32_t)__popcll(md) >= lp.decide_min || __ballot(mode == kStep) == 0)) {
-        policy_wave(s.policy, s_feat, md, lane);  // the whole wave: matrix-core operands span all lanes
         if (mode == kDecide) {
-          const float4 lg = reinterpret_cast<const float4*>(s_feat)[2 * lane];
+          // inputs of the node one level up (the u-split just taken), with the direction in
+          // the frame the patch is subdivided in
+          const float fdx = s.frames ? 1.0f / wr.ix : s_dir[0][lane];
+          const float fdy = s.frames ? 1.0f / wr.iy : s_dir[1][lane];
+          const float fdz = s.frames ? 1.0f / wr.iz : s_dir[2][lane];
+          float f[16];
+          policy_features(policy_load_node(s_feat, lane, s_mirror[lane]), pox, poy, poz, fdx, fdy, fdz, depth - 1,
+                          s.leaf_depth, (pmeta & kGregoryBit) != 0, f);
+          policy_store_inputs<16>(s_feat, lane, f);
+        }
+        policy_wave<16>(s.policy, s_feat, md, lane);  // the whole wave: matrix-core operands span all lanes
+        if (mode == kDecide) {
+          const float4 lg = reinterpret_cast<const float4*>(s_feat)[4 * lane];
           const uint32_t top = policy_top(lg.x, lg.y, lg.z, lg.w);
           const uint32_t bit = 1u << (L2 - depth);  // path bit of the u-split just taken
           vpref = 1u | ((top & 1u) << 1);
@@ -343,14 +361,14 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
       // the chosen half replaces the grid on every path: when the lane backtracks or
       // leaves the patch instead, the grid is rebuilt before it is read again
       const bool second = go_up != mir;
-      float ocx[2], ocy[2], ocz[2];  // learned order: the node's corners at the other storage end
       if (kLearned && decide) {
-        ocx[0] = second ? ex[0].v[0] : ex[0].v[6];
-        ocx[1] = second ? ex[3].v[0] : ex[3].v[6];
-        ocy[0] = second ? ey[0].v[0] : ey[0].v[6];
-        ocy[1] = second ? ey[3].v[0] : ey[3].v[6];
-        ocz[0] = second ? ez[0].v[0] : ez[0].v[6];
-        ocz[1] = second ? ez[3].v[0] : ez[3].v[6];
+        // the node's corners in storage order (0,0), (3,0), (0,3), (3,3) and its slab
+        // results, kept for the decision (formed there, off this phase's registers)
+        const float sx[4] = {ex[0].v[0], ex[0].v[6], ex[3].v[0], ex[3].v[6]};
+        const float sy[4] = {ey[0].v[0], ey[0].v[6], ey[3].v[0], ey[3].v[6]};
+        const float sz[4] = {ez[0].v[0], ez[0].v[6], ez[3].v[0], ez[3].v[6]};
+        policy_store_node(s_feat, lane, sx, sy, sz, sp2);
+        s_mirror[lane] = (uint8_t)mirror0;
       }
       take_half(ex, second, G.x);
       take_half(ey, second, G.y);
@@ -375,32 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(DeviceScene s, BatchTable bt, 
           if (second) mirror ^= (1u << axis);
           depth++;
           if (pmeta & kGregoryBit) mode = kGrid;  // Alg. 3 recomputes a Gregory grid at every node
-          if (kLearned && decide) {
-            // the node's corners in storage order (0,0), (3,0), (0,3), (3,3): the taken
-            // end is now the first column of G
-            float sx[4], sy[4], sz[4];
-            sx[0] = second ? ocx[0] : G.x[0][0];
-            sx[1] = second ? G.x[0][0] : ocx[0];
-            sx[2] = second ? ocx[1] : G.x[3][0];
-            sx[3] = second ? G.x[3][0] : ocx[1];
-            sy[0] = second ? ocy[0] : G.y[0][0];
-            sy[1] = second ? G.y[0][0] : ocy[0];
-            sy[2] = second ? ocy[1] : G.y[3][0];
-            sy[3] = second ? G.y[3][0] : ocy[1];
-            sz[0] = second ? ocz[0] : G.z[0][0];
-            sz[1] = second ? G.z[0][0] : ocz[0];
-            sz[2] = second ? ocz[1] : G.z[3][0];
-            sz[3] = second ? G.z[3][0] : ocz[1];
-            float f[16];
-            // the direction in the frame the patch is subdivided in
-            const float fdx = s.frames ? 1.0f / wr.ix : s_dir[0][lane];
-            const float fdy = s.frames ? 1.0f / wr.iy : s_dir[1][lane];
-            const float fdz = s.frames ? 1.0f / wr.iz : s_dir[2][lane];
-            policy_inputs(sx, sy, sz, mirror0, pox, poy, poz, fdx, fdy, fdz, sp2, depth - 1, s.leaf_depth,
-                          (pmeta & kGregoryBit) != 0, f);
-            policy_store_inputs(s_feat, lane, f);
-            mode = kDecide;
-          }
+          if (kLearned && decide) mode = kDecide;
         }
       }
       if (backtrack) {
