@@ -302,7 +302,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     // ----------------------------- learned order: the network for waiting lanes
     if (kLearned) {
       const uint64_t md = __ballot(mode == kDecide);
-      if (md != 0 && ((uint32_t)__popcll(md) >= lp.decide_min || __ballot(mode == kStep) == 0)) {
+      const uint32_t n_dec = (uint32_t)__popcll(md);
+      if (md != 0 && (n_dec >= lp.decide_min || __ballot(mode == kStep) == 0)) {
+        // deciding lanes take consecutive slots, so the network runs on ceil(n / 16)
+        // column tiles instead of every tile holding one of them (all slot reads of
+        // the node values precede the first input store in the wave's program order)
+        const uint32_t slot = (uint32_t)__popcll(md & ((1ull << lane) - 1ull));
         if (mode == kDecide) {
           // inputs of the node one level up (the u-split just taken), with the direction in
           // the frame the patch is subdivided in
@@ -312,11 +317,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           float f[16];
           policy_features(policy_load_node(s_feat, lane, s_mirror[lane]), pox, poy, poz, fdx, fdy, fdz, depth - 1,
                           s.leaf_depth, (pmeta & kGregoryBit) != 0, f);
-          policy_store_inputs<16>(s_feat, lane, f);
+          policy_store_inputs<16>(s_feat, (int)slot, f);
         }
-        policy_wave<16>(s.policy, s_feat, md, lane);  // the whole wave: matrix-core operands span all lanes
+        const uint64_t need = n_dec >= 64 ? ~0ull : (1ull << n_dec) - 1ull;
+        policy_wave<16>(s.policy, s_feat, need, lane);  // the whole wave: matrix-core operands span all lanes
         if (mode == kDecide) {
-          const float4 lg = reinterpret_cast<const float4*>(s_feat)[4 * lane];
+          const float4 lg = reinterpret_cast<const float4*>(s_feat)[4 * slot];
           const uint32_t top = policy_top(lg.x, lg.y, lg.z, lg.w);
           const uint32_t bit = 1u << (L2 - depth);  // path bit of the u-split just taken
           vpref = 1u | ((top & 1u) << 1);
