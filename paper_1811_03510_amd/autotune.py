@@ -79,9 +79,28 @@ def time_launch(scene, batches, reps: int = 3) -> float:
     return statistics.median(ts)
 
 
+def confirm(scene, batches, cands: list, rounds: int = 5, log=None) -> tuple[dict, float]:
+    """The fastest of ``cands`` by the median of ``rounds`` timings each, taken
+    round-robin so that clock drift affects every candidate alike."""
+    times = [[] for _ in cands]
+    for _ in range(rounds):
+        for i, p in enumerate(cands):
+            scene.set_launch(**p)
+            times[i].append(time_launch(scene, batches, 1))
+    med = [statistics.median(t) for t in times]
+    k = min(range(len(cands)), key=lambda i: med[i])
+    if log:
+        for p, m in zip(cands, med):
+            log(f"autotune confirm {p} -> {m:.3f} ms")
+    scene.set_launch(**cands[k])
+    return dict(cands[k]), med[k]
+
+
 def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None,
-         learned: bool = False) -> tuple[dict, float, list]:
-    """Coordinate descent over ``space`` from DEFAULT.  Returns (params, ms, trials)."""
+         learned: bool = False, finalists: int = 4) -> tuple[dict, float, list]:
+    """Coordinate descent over ``space`` from DEFAULT, then the ``finalists``
+    fastest settings seen (and DEFAULT) timed again side by side (confirm).
+    Returns (params, ms, trials)."""
     space = dict(space or SPACE)
     if not learned:
         space.pop("decide_min", None)
@@ -110,6 +129,12 @@ def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None,
                     best, best_ms, improved = cand, ms, True
         if not improved:
             break
+    if finalists > 1:
+        ranked = sorted(seen.items(), key=lambda kv: kv[1])[:finalists]
+        cands = [dict(k) for k, _ in ranked]
+        if dict(DEFAULT) not in cands:
+            cands.append(dict(DEFAULT))
+        best, best_ms = confirm(scene, batches, cands, log=log)
     scene.set_launch(**best)
     return best, best_ms, trials
 

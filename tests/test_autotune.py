@@ -41,6 +41,29 @@ def test_coordinate_descent_finds_the_minimum(monkeypatch):
     assert any(t["decide_min"] != autotune.DEFAULT["decide_min"] for t, _ in trials_l)
 
 
+def test_confirmation_round_overrules_a_lucky_sample(monkeypatch):
+    # DEFAULT with fetch_min 48 is truly slow, but its first timing is a lucky outlier
+    # that the descent accepts (and then finds nothing faster around it); timed again
+    # side by side with the other finalists it loses
+    lucky = dict(autotune.DEFAULT, fetch_min=48)
+    count = {"lucky": 0}
+
+    def noisy(scene, batches, reps=3):
+        if scene.p == lucky:
+            count["lucky"] += 1
+            return 0.5 if count["lucky"] == 1 else 2.0
+        return fake_time(scene, batches, reps)
+    monkeypatch.setattr(autotune, "time_launch", noisy)
+    best1, _, _ = autotune.tune(FakeScene(), [], finalists=1)  # descent alone: the outlier wins
+    assert best1 == lucky
+    count["lucky"] = 0
+    sc = FakeScene()
+    best, ms, _ = autotune.tune(sc, [])
+    assert best != lucky and sc.p == best
+    sc.p = best
+    assert ms == pytest.approx(fake_time(sc, [])) and ms < 2.0
+
+
 def test_results_are_cached_by_key(monkeypatch, tmp_path):
     monkeypatch.setattr(autotune, "time_launch", fake_time)
     monkeypatch.setattr(autotune, "workload_key", lambda scene, batches: "w1")
