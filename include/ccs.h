@@ -128,7 +128,8 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out);
  * boxes are recomputed, then the BVH node boxes level by level from the deepest
  * (one launch per level); the topology is unchanged.  Asynchronous on `stream`;
  * device input must be 16-byte aligned and stay valid until the stream passes
- * this call.  Host input is copied before return.
+ * this call.  Host input is staged in a per-scene device buffer and the call
+ * returns when the refit is done (synchronous).
  * Host input is scanned for non-finite values (CCS_ERR_INVALID_ARG); device input
  * is not scanned (non-finite points then give unspecified hits, never a fault). */
 ccs_status ccs_refit(ccs_scene* scene, const float* control_points, int32_t location, void* stream);
@@ -168,7 +169,7 @@ ccs_status ccs_intersect_batched(const ccs_scene* scene, const ccs_batch* batche
  * `stream`.  Deterministic: the result of each ray does not depend on launch
  * geometry or on the other rays.  Each call takes one of 256 per-scene
  * ray-queue counters in turn: at most 256 calls on one scene may be in flight
- * at once (across all streams). */
+ * at once (across all streams).  At most 2^31 - 1 rays (CCS_ERR_INVALID_ARG). */
 ccs_status ccs_intersect(const ccs_scene* scene, const ccs_ray* rays, uint32_t n, ccs_hit* hits,
                          void* stream);
 

@@ -28,6 +28,7 @@ EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_coun
            "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train",
            "ccs_bounce_frame", "ccs_device_bytes_in_use")
 MAX_BATCHES = 32
+MAX_RAYS = (1 << 31) - 1  # per call
 POLICY_PARAMS = 1732
 NO_LABEL = 255
 
@@ -199,6 +200,7 @@ class Scene:
             r = self._rays(rays)
             if hits is None:
                 hits = torch.empty((r.shape[0], 4), dtype=torch.float32, device=r.device)
+            hits = _out(hits, r.shape[0], 4, torch.float32, "hits")
             arr[k] = Batch(int(frame), r.shape[0], r.data_ptr(), hits.data_ptr())
             out.append(hits)
         _check(lib().ccs_intersect_batched(self._h, arr, len(batches), _stream(stream)))
@@ -242,8 +244,10 @@ class Scene:
     def _rays(rays):
         import torch
         r = torch.as_tensor(rays)
-        if not r.is_cuda or r.dtype != torch.float32 or r.shape[-1] != 8 or not r.is_contiguous():
+        if not r.is_cuda or r.dtype != torch.float32 or r.dim() != 2 or r.shape[1] != 8 or not r.is_contiguous():
             raise ValueError("rays must be a contiguous (N, 8) float32 CUDA tensor")
+        if r.shape[0] > MAX_RAYS:
+            raise ValueError(f"at most {MAX_RAYS} rays per call")
         return r
 
     def intersect(self, rays, hits=None, stream=None):
@@ -253,6 +257,7 @@ class Scene:
         n = r.shape[0]
         if hits is None:
             hits = torch.empty((n, 4), dtype=torch.float32, device=r.device)
+        hits = _out(hits, n, 4, torch.float32, "hits")
         _check(lib().ccs_intersect(self._h, _ptr(r), n, _ptr(hits), _stream(stream)))
         return hits
 
@@ -285,8 +290,20 @@ class Scene:
             raise ValueError("hits (N, 4) and uniforms (N, 2) must be contiguous float32 CUDA tensors")
         if out is None:
             out = torch.empty_like(r)
+        out = _out(out, n, 8, torch.float32, "out")
+        if out.data_ptr() == r.data_ptr():
+            raise ValueError("out must not alias rays")
         _check(lib().ccs_bounce_frame(self._h, int(frame), _ptr(r), _ptr(h), _ptr(u), n, _ptr(out), _stream(stream)))
         return out
+
+
+def _out(t, n: int, width: int, dtype, name: str):
+    """A caller-supplied output tensor: the kernel writes exactly n x width values into it."""
+    import torch
+    t = torch.as_tensor(t)
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != (n, width):
+        raise ValueError(f"{name} must be a contiguous ({n}, {width}) {dtype} CUDA tensor")
+    return t
 
 
 def _params(params):

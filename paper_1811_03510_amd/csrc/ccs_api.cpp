@@ -485,6 +485,9 @@ ccs_status ccs_refit_frame(ccs_scene* s, uint32_t frame, const float* control_po
   if (f.frames) f.frames = s->dev.frames + frame * s->dev.frame_frames_f4;
   hipError_t e = ccs::launch_refit(f, src, s->level_offsets.data(), (uint32_t)s->level_offsets.size() - 1, st);
   if (e != hipSuccess) return hip_fail(e, "refit launch");
+  // host input goes through the scene's one staging buffer: wait until the refit has
+  // read it, so that a refit on another stream cannot overwrite it meanwhile
+  if (location == CCS_HOST && (e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "host refit");
   return CCS_OK;
 }
 
@@ -514,11 +517,16 @@ static ccs::BatchTable one_batch(const ccs_ray* rays, uint32_t n, ccs_hit* hits)
   return bt;
 }
 
+// The persistent kernel hands out rays from a 32-bit counter that overshoots n by
+// at most 64 per resident wave: below 2^31 rays it cannot wrap.
+constexpr uint32_t kMaxRaysPerCall = (1u << 31) - 1u;
+
 ccs_status ccs_intersect(const ccs_scene* s, const ccs_ray* rays, uint32_t n, ccs_hit* hits, void* stream) {
   g_error.clear();
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n == 0) return CCS_OK;
   if (!rays || !hits) return fail(CCS_ERR_INVALID_ARG, "rays or hits is NULL");
+  if (n > kMaxRaysPerCall) return fail(CCS_ERR_INVALID_ARG, "more than 2^31 - 1 rays in one call");
   return launch_batches(s, one_batch(rays, n, hits), nullptr, stream);
 }
 
@@ -528,6 +536,7 @@ ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n == 0) return CCS_OK;
   if (!rays || !hits || !counters) return fail(CCS_ERR_INVALID_ARG, "rays, hits or counters is NULL");
+  if (n > kMaxRaysPerCall) return fail(CCS_ERR_INVALID_ARG, "more than 2^31 - 1 rays in one call");
   return launch_batches(s, one_batch(rays, n, hits), counters, stream);
 }
 
@@ -551,7 +560,7 @@ ccs_status ccs_intersect_batched(const ccs_scene* s, const ccs_batch* batches, u
     bt.hits[b] = x.hits;
     total += x.n;
   }
-  if (total >= (1ull << 31)) return fail(CCS_ERR_INVALID_ARG, "more than 2^31 rays in one call");
+  if (total > kMaxRaysPerCall) return fail(CCS_ERR_INVALID_ARG, "more than 2^31 - 1 rays in one call");
   bt.prefix[n_batches] = (uint32_t)total;
   if (total == 0) return CCS_OK;
   return launch_batches(s, bt, nullptr, stream);

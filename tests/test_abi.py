@@ -126,3 +126,15 @@ def test_policy_and_batch_entry_points_validate_on_the_host():
     assert L.ccs_refit_frame(None, 0, fake, 1, None) == ccs.CCS_ERR_INVALID_ARG
     p = ccs.LaunchParams(0, 16, 1, 16, 2, 0)
     assert L.ccs_scene_set_launch(None, C.byref(p)) == ccs.CCS_ERR_INVALID_ARG
+
+
+def test_ray_count_bound_is_checked_before_any_launch():
+    # the persistent kernel's 32-bit ray counter must not wrap: 2^31 rays or more
+    # are refused on the host (the scene pointer is not dereferenced on this path)
+    L = ccs.lib()
+    fake = C.c_void_p(16)
+    for n in ((1 << 31), (1 << 32) - 1):
+        assert L.ccs_intersect(fake, fake, n, fake, None) == ccs.CCS_ERR_INVALID_ARG
+        assert "2^31" in L.ccs_last_error().decode()
+        assert L.ccs_intersect_counted(fake, fake, n, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
+

@@ -92,3 +92,26 @@ def test_malformed_cap_is_an_argument_error(ccs, c1, cap):
     with pytest.raises(ccs.CcsError) as e:
         ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
     assert e.value.status == ccs.CCS_ERR_INVALID_ARG and ENV in str(e.value)
+
+
+def test_binding_rejects_outputs_the_kernels_would_overrun(ccs, c1):
+    sc = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), c1.leaf_depth)
+    rays = torch.from_numpy(c1.primary[:1000]).cuda()
+    for bad in (torch.empty((999, 4), device="cuda"), torch.empty((1000, 4), device="cuda", dtype=torch.float64),
+                torch.empty((4, 1000), device="cuda").t(), torch.empty((1000, 4))):
+        with pytest.raises(ValueError):
+            sc.intersect(rays, bad)
+        with pytest.raises(ValueError):
+            sc.intersect_batched([(0, rays, bad)])
+    with pytest.raises(ValueError):
+        sc.intersect(rays.reshape(10, 100, 8))
+    hits = sc.intersect(rays)
+    u = torch.rand((1000, 2), device="cuda")
+    with pytest.raises(ValueError):
+        sc.bounce(rays, hits, u, out=torch.empty((999, 8), device="cuda"))
+    with pytest.raises(ValueError):
+        sc.bounce(rays, hits, u, out=rays)
+    out = sc.bounce(rays, hits, u)
+    torch.cuda.synchronize()
+    assert out.shape == (1000, 8) and torch.isfinite(out[:, :3]).all()
+    sc.close()
