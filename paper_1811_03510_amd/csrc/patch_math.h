@@ -312,6 +312,67 @@ __device__ __forceinline__ void calc_points_and_d(const PatchPts& P, bool gregor
   crop_component(gz, mu, mv, qz);
 }
 
+// One component (x, y or z) of calc_points_and_d, with the same operations in
+// the same order: rc holds the record's 16 grid values of the component (slot
+// 4j + i at rc[4j + i]), rv its four P^v values.  Used when the three components
+// of a lane's grid are computed by three lanes.
+__device__ __forceinline__ void calc_component(const float* __restrict__ rc, const float* __restrict__ rv,
+                                               bool gregory, float u0, float u1, float v0, float v1, float q[4][4],
+                                               float& d) {
+  float g[4][4];
+  const float4* r4 = reinterpret_cast<const float4*>(rc);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float4 x = r4[j];
+    g[0][j] = x.x;
+    g[1][j] = x.y;
+    g[2][j] = x.z;
+    g[3][j] = x.w;
+  }
+  d = 0.0f;
+  if (gregory) {
+    const float4 pv = *reinterpret_cast<const float4*>(rv);
+    const float vv[4] = {pv.x, pv.y, pv.z, pv.w};
+    const float wu1 = wbar1(u0, u1), wu2 = wbar2(u0, u1), wv1 = wbar1(v0, v1), wv2 = wbar2(v0, v1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = (k & 1) ? 2 : 1, j = (k & 2) ? 2 : 1;
+      const float dul = (i == 1) ? u0 : 1.0f - u1, duh = (i == 1) ? u1 : 1.0f - u0;
+      const float dvl = (j == 1) ? v0 : 1.0f - v1, dvh = (j == 1) ? v1 : 1.0f - v0;
+      const float lam_lo = dul * __builtin_amdgcn_rcpf(dul + dvh), lam_hi = duh * __builtin_amdgcn_rcpf(duh + dvl);
+      const float w = ((i == 1) ? wu1 : wu2) * ((j == 1) ? wv1 : wv2);
+      const float e = g[i][j] - vv[k];
+      const float a = fmaf(lam_lo, e, vv[k]), b = fmaf(lam_hi, e, vv[k]);
+      g[i][j] = fminf(a, b);
+      d = fmaf(w, fabsf(a - b), d);
+    }
+  }
+  const Crop4 mu = crop_matrix(u0, u1), mv = crop_matrix(v0, v1);
+  crop_component(g, mu, mv, q);
+}
+
+// Position of the r-th set bit (from 0) of m; r < popcount(m).
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+  uint32_t pos = 0;
+  uint32_t c = (uint32_t)__popc((uint32_t)m);
+  if (r >= c) {
+    r -= c;
+    m >>= 32;
+    pos = 32;
+  }
+  uint32_t x = (uint32_t)m;
+#pragma unroll
+  for (int w = 16; w >= 1; w >>= 1) {
+    c = (uint32_t)__popc(x & ((1u << w) - 1u));
+    if (r >= c) {
+      r -= c;
+      x >>= w;
+      pos += (uint32_t)w;
+    }
+  }
+  return pos;
+}
+
 // Bits of a 2L-bit interleaved path code: split k (0-based, u at even k) owns bit
 // 2L-1-k, so u bits sit at odd and v bits at even positions.
 __device__ __forceinline__ uint32_t compact_even(uint32_t x) {

@@ -39,6 +39,7 @@
 namespace ccs {
 
 constexpr int kBlock = 64;
+constexpr uint32_t kGridOwners = kBlock / 3;  // lanes whose grids one recompute phase serves
 
 enum Mode : int { kFetch = 0, kTraverse = 1, kStep = 2, kGrid = 3, kDead = 4, kDecide = 5 };
 
@@ -267,31 +268,68 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 
     // ---------------------------------------------- recompute grids in a batch
+    // Three lanes per waiting lane: the lane of rank r among those waiting (the
+    // owner) has the x, y and z components of its grid computed by lanes 3r, 3r+1
+    // and 3r+2 (helpers, whatever their own mode), each with the arithmetic of
+    // calc_points_and_d for its component, and pulls them back.  At most
+    // kGridOwners lanes are served per phase; the others wait for the next one.
     if (mg != 0 && ((uint32_t)__popcll(mg) >= lp.grid_min || ms == 0)) {
-      if (mode == kGrid) {
-        // domain of the node at `depth`: position from the path code, sizes from the depth
-        const float u0 = (float)compact_even(code >> 1) * leaf_scale;
-        const float v0 = (float)compact_even(code) * leaf_scale;
-        const float su = __uint_as_float((uint32_t)(127 - ((depth + 1) >> 1)) << 23);
-        const float sv = __uint_as_float((uint32_t)(127 - (depth >> 1)) << 23);
-        const bool greg = (pmeta & kGregoryBit) != 0;
-        PatchPts P;
-        load_grid(recs + (size_t)rec_idx * kRecFloats, P, greg);
-        float qx[4][4], qy[4][4], qz[4][4];
-        calc_points_and_d(P, greg, u0, u0 + su, v0, v0 + sv, qx, qy, qz, dx, dy, dz);
-        if (s.frames) {
-          dx += pad2;
-          dy += pad2;
-          dz += pad2;
+      const uint32_t n_wait = (uint32_t)__popcll(mg);
+      const uint32_t n_own = n_wait < kGridOwners ? n_wait : kGridOwners;
+      const uint32_t rank = (uint32_t)__popcll(mg & ((1ull << lane) - 1ull));
+      const bool owner = mode == kGrid && rank < n_own;
+      const uint32_t hr = (uint32_t)lane / 3u, hc = (uint32_t)lane - 3u * hr;
+      const bool helper = hr < n_own;
+      // the owner's record, path code, depth and type, read by its helpers
+      const int from = (int)nth_set_bit(mg, helper ? hr : 0u) * 4;
+      const uint64_t rp = reinterpret_cast<uint64_t>(recs + (size_t)rec_idx * kRecFloats);
+      const uint32_t dg = (uint32_t)depth | ((pmeta & kGregoryBit) ? 0x100u : 0u);
+      const uint32_t h_lo = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)rp);
+      const uint32_t h_hi = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(rp >> 32));
+      const uint32_t h_code = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)code);
+      const uint32_t h_dg = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)dg);
+      float qo[4][4], dc = 0.0f;
+      if (helper) {
+        const float* hrec = reinterpret_cast<const float*>(((uint64_t)h_hi << 32) | h_lo);
+        const int hd = (int)(h_dg & 0xFFu);
+        // domain of the node at depth hd: position from the path code, sizes from the depth
+        const float u0 = (float)compact_even(h_code >> 1) * leaf_scale;
+        const float v0 = (float)compact_even(h_code) * leaf_scale;
+        const float su = __uint_as_float((uint32_t)(127 - ((hd + 1) >> 1)) << 23);
+        const float sv = __uint_as_float((uint32_t)(127 - (hd >> 1)) << 23);
+        float q[4][4];
+        calc_component(hrec + 16 * hc, hrec + 48 + 4 * hc, (h_dg & 0x100u) != 0, u0, u0 + su, v0, v0 + sv, q, dc);
+        orient(q, (hd & 1) != 0, qo);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) qo[a][b] = 0.0f;
+      }
+      const int to = owner ? (int)(12u * rank) : 0;  // byte index of the owner's x helper
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int v = __float_as_int(qo[a][b]);
+          const float gx = __int_as_float(__builtin_amdgcn_ds_bpermute(to, v));
+          const float gy = __int_as_float(__builtin_amdgcn_ds_bpermute(to + 4, v));
+          const float gz = __int_as_float(__builtin_amdgcn_ds_bpermute(to + 8, v));
+          G.x[a][b] = owner ? gx : G.x[a][b];
+          G.y[a][b] = owner ? gy : G.y[a][b];
+          G.z[a][b] = owner ? gz : G.z[a][b];
         }
-        const bool along_v = (depth & 1) != 0;
-        orient(qx, along_v, G.x);
-        orient(qy, along_v, G.y);
-        orient(qz, along_v, G.z);
+      const float ddx = __int_as_float(__builtin_amdgcn_ds_bpermute(to, __float_as_int(dc)));
+      const float ddy = __int_as_float(__builtin_amdgcn_ds_bpermute(to + 4, __float_as_int(dc)));
+      const float ddz = __int_as_float(__builtin_amdgcn_ds_bpermute(to + 8, __float_as_int(dc)));
+      if (owner) {
+        dx = ddx + pad2;  // pad2 is 0 outside patch-local frames
+        dy = ddy + pad2;
+        dz = ddz + pad2;
         mirror = 0;
         mode = kStep;
         if (kStats) {
-          if (greg)
+          if (pmeta & kGregoryBit)
             cnt.greg++;
           else
             cnt.crop++;
