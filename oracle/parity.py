@@ -49,6 +49,16 @@ def _path_in_box(ray, lo, hi):
     return (far - near) * np.linalg.norm(d)  # negative when the box is missed
 
 
+def _in_frame(osc, pid, ray):
+    """The ray with origin and direction mapped by patch pid's frame rows (the
+    identity in world coordinates), as the oracle's boxes of that patch are."""
+    R = osc.patch_frame(int(pid))
+    out = np.array(ray, dtype=np.float64)
+    out[:3] = R @ out[:3]
+    out[4:7] = R @ out[4:7]
+    return out
+
+
 def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: float, leaf_depth: int,
          min_match: float = 0.9999, label: str = "") -> dict:
     """Compares GPU hits (N, 4) float32 with oracle hits; returns a report dict."""
@@ -99,13 +109,14 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
                 if dist <= np.linalg.norm(hi - lo) + 1e-6 * (abs(gt[k]) + 1.0):
                     kind = "tangent"
         if kind == "hard":
-            # the side that hit: does the ray merely clip its leaf box?
+            # the side that hit: does the ray merely clip its leaf box?  (The box is in
+            # the patch's frame, where the ray is taken too.)
             for side_hit, pid, u, v, t in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k], ora["t"][k]),
                                            (g_hit[k], gid[k], gpu[k, 2], gpu[k, 3], gt[k])):
                 if side_hit:
                     lo, hi = osc.leaf_box(pid, u, v)
                     slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-6 * (abs(t) + 1.0)
-                    if abs(_path_in_box(ray, lo, hi)) <= slack:
+                    if abs(_path_in_box(_in_frame(osc, pid, ray), lo, hi)) <= slack:
                         kind = "graze"
                         break
         kinds[kind] += 1

@@ -112,6 +112,16 @@ struct RayP {  // a ray in some frame: origin, reciprocal direction, tmin
 // to the distance itself, which is what the widening covers (a precomputed
 // -o/d would carry an error relative to |o|/|d|, not to the distance).
 constexpr float kFarScale = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);
+// The same widening for a negative far distance (patch-frame distances are measured
+// from the ray's point closest to the patch anchor, so a box the ray leaves before
+// that point has a negative far distance): 1 - 2 (kFarScale - 1), at least 2 gamma_3
+// below 1 after rounding.
+constexpr float kFarShrink = 1.0f - 2.0f * (kFarScale - 1.0f);
+
+// A far distance moved outwards by 2 gamma_3 of its magnitude, whatever its sign
+// (a plain product by kFarScale would pull a negative one inwards, and a box of zero
+// thickness, where entry equals exit, would then be missed).
+__device__ __forceinline__ float widen_far(float f) { return f * (f >= 0.0f ? kFarScale : kFarShrink); }
 
 __device__ __forceinline__ float safe_inv(float d) {
   // a zero component gets a huge finite reciprocal: the slab of that axis is then
@@ -166,7 +176,7 @@ __device__ __forceinline__ float slab(const RayP& r, float lx, float ly, float l
   const float ty0 = (ly - r.oy) * r.iy, ty1 = (hy - r.oy) * r.iy;
   const float tz0 = (lz - r.oz) * r.iz, tz1 = (hz - r.oz) * r.iz;
   const float nr = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), r.tmin));
-  float fr = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * kFarScale;
+  float fr = widen_far(fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)));
   fr = fminf(fr, cap);
   return nr <= fr ? nr : __builtin_inff();
 }

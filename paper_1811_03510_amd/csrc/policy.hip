@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64) void k_record(DeviceScene s, const ccs_ray* __r
     split_fold(G.z, poz, iz, dz, e, sp);
     // no cap: the reported hit lies on the boxes' boundary as often as not, and a
     // capped test there would turn on rounding
-    const bool ha = sp.na <= sp.fa * kFarScale, hb = sp.nb <= sp.fb * kFarScale;
+    const bool ha = sp.na <= widen_far(sp.fa), hb = sp.nb <= widen_far(sp.fb);
     if (ha && hb) {
       const float sx[4] = {qx[0][0], qx[3][0], qx[0][3], qx[3][3]};
       const float sy[4] = {qy[0][0], qy[3][0], qy[0][3], qy[3][3]};

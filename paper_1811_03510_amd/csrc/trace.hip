@@ -241,8 +241,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         const float4* nd = nodes + 4 * (size_t)cur;
         const float4 a = nd[0], b = nd[1], c = nd[2], e = nd[3];
         const int c0 = __float_as_int(e.x), c1 = __float_as_int(e.y);
-        const float t0 = slab(wr, a.x, a.y, a.z, a.w, b.x, b.y, best_t);
-        const float t1 = slab(wr, b.z, b.w, c.x, c.y, c.z, c.w, best_t);
+        // the cap is widened by a few ulps so that a box entered at the best distance
+        // itself is never lost to rounding (equal distances go to the lower patch id)
+        const float capw = best_t + fabsf(best_t) * 0x1p-21f;
+        const float t0 = slab(wr, a.x, a.y, a.z, a.w, b.x, b.y, capw);
+        const float t1 = slab(wr, b.z, b.w, c.x, c.y, c.z, c.w, capw);
         const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
         if (h0 && h1) {
           const bool first1 = t1 < t0;
@@ -383,8 +386,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       split_fold(G.x, pox, wr.ix, dx, ex, sp2);
       split_fold(G.y, poy, wr.iy, dy, ey, sp2);
       split_fold(G.z, poz, wr.iz, dz, ez, sp2);
-      const float cap = best_t - pt0;  // the best distance in the patch frame
-      const float fa = fminf(sp2.fa * kFarScale, cap), fb = fminf(sp2.fb * kFarScale, cap);
+      // the best distance in the patch frame: best_t - pt0 carries the rounding of
+      // best_t = pt0 + t and of the difference (each at most 2^-24 relative), so it
+      // is widened by twice their bound and a leaf at the best distance is never pruned
+      const float cap = (best_t - pt0) + (fabsf(best_t) + fabsf(pt0)) * 0x1p-22f;
+      const float fa = fminf(widen_far(sp2.fa), cap), fb = fminf(widen_far(sp2.fb), cap);
       const bool ha = sp2.na <= fa, hb = sp2.nb <= fb;
       const float ta = sp2.na, tb = sp2.nb;
       const int axis = depth & 1;

@@ -1,0 +1,118 @@
+"""GPU parity on scenes at the edges of the arithmetic: the 512-patch torus far
+from the origin (anchoring, Sec. 3.4, and the double-precision patch frame), exact
+duplicate patches (equal distances resolve to the lowest patch id), and patches
+collapsed to a line or a point (zero-extent boxes, degenerate local frames)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.parity import assert_gate, gate, ids_of
+from paper_1811_03510_amd import scenes as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ccs():
+    from paper_1811_03510_amd import ccs as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def _run(scene, rays):
+    h = scene.intersect(torch.from_numpy(np.ascontiguousarray(rays, dtype=np.float32)).cuda())
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+def _both(ccs, cp, ty, L, local):
+    return (ccs.Scene(torch.from_numpy(cp).cuda(), torch.from_numpy(ty).cuda(), L, local_frames=local),
+            O.Scene(cp, ty, L, local_frames=local))
+
+
+@pytest.mark.parametrize("local", [False, True], ids=["world", "local"])
+def test_torus_far_from_the_origin(ccs, c1, local):
+    # moved by about 2600 diameters: coordinates near 1e4 keep 2^-24 relative precision, and
+    # anchored points and patch-frame rays keep the hits as exact as at the origin
+    off = np.array([1.0e4, -6.0e3, 4.5e3])
+    cp = (c1.cp.astype(np.float64) + off).astype(np.float32)
+    rays = np.concatenate([c1.primary, c1.diffuse]).copy()
+    rays[:, :3] = (rays[:, :3].astype(np.float64) + off).astype(np.float32)
+    _say(f"torus moved by {off}, {len(rays)} rays (local frames: {local})")
+    gsc, osc = _both(ccs, cp, c1.types, c1.leaf_depth, local)
+    g = _run(gsc, rays)
+    o = osc.intersect(rays)
+    rep = gate(g, o, rays, osc, c1.diameter, c1.leaf_depth, label=f"far-{'local' if local else 'world'}")
+    assert_gate(rep)
+    assert (ids_of(g) != O.NO_HIT).sum() > 5000
+
+
+@pytest.mark.parametrize("local", [False, True], ids=["world", "local"])
+def test_duplicate_patches_resolve_to_the_lowest_id(ccs, c1, local):
+    n = 128
+    cp = np.ascontiguousarray(np.concatenate([c1.cp[:n]] * 3))
+    ty = np.ascontiguousarray(np.concatenate([c1.types[:n]] * 3))
+    gsc, osc = _both(ccs, cp, ty, c1.leaf_depth, local)
+    rays = np.concatenate([c1.primary, c1.diffuse])
+    g = _run(gsc, rays)
+    o = osc.intersect(rays)
+    assert_gate(gate(g, o, rays, osc, c1.diameter, c1.leaf_depth, label="duplicates"))
+    gid = ids_of(g)
+    hit = gid != O.NO_HIT
+    assert hit.sum() > 1000
+    # identical copies give bit-identical distances, so a hit names the first copy; the
+    # exception is a Gregory copy whose path the best distance prunes at an ancestor
+    # whose recomputed bound is not nested around the leaf (Alg. 3 tests children
+    # against the current best distance): then the copy reached first keeps the hit, on
+    # the oracle's side as well
+    bez = hit & (ty[np.where(hit, gid, 0)] == 0)
+    assert np.all(gid[bez] < n)
+    assert (gid[hit] >= n).sum() <= max(2, hit.sum() // 1000)
+    # distances, (u, v) and the patch modulo the copy equal those of the scene holding
+    # only the first copy
+    g1 = _run(ccs.Scene(torch.from_numpy(np.ascontiguousarray(c1.cp[:n])).cuda(),
+                        torch.from_numpy(np.ascontiguousarray(c1.types[:n])).cuda(), c1.leaf_depth,
+                        local_frames=local), rays)
+    for col in (0, 2, 3):
+        assert np.array_equal(g[:, col].view(np.uint32), g1[:, col].view(np.uint32)), col
+    assert np.array_equal(np.where(hit, gid % n, gid), ids_of(g1))
+
+
+@pytest.mark.parametrize("local", [False, True], ids=["world", "local"])
+def test_collapsed_patches(ccs, local):
+    rng = np.random.default_rng(7)
+    a, e = np.array([3.3, -0.2, 0.1]), np.array([1.0, 0.5, -0.25])
+    line = np.array([a + (i / 3) * e for j in range(4) for i in range(4)])          # every row the same segment
+    point = np.tile(a + 0.5 * e, (16, 1))                                           # all points equal
+    flat = np.array([[i / 3 - 0.5, j / 3 - 0.5, -1.0] for j in range(4) for i in range(4)])  # a regular square
+    flat_g = flat + np.array([1.25, 0.0, 0.0])                                      # its Gregory twin, beside it
+    cp = np.stack([np.concatenate([g, g[[5, 6, 9, 10]]]) for g in (line, point, flat, line, point, flat_g)])
+    cp = cp.astype(np.float32)
+    ty = np.array([0, 0, 0, 1, 1, 1], np.uint8)                                     # Bezier and Gregory tags
+    gsc, osc = _both(ccs, cp, ty, 8, local)
+    n = 4096
+
+    def rays_to(origins, targets):
+        r = np.zeros((len(origins), 8), np.float32)
+        r[:, :3], r[:, 4:7], r[:, 7] = origins, targets - origins, np.inf
+        return r
+    # rays to the square, away from the collapsed patches: strict parity
+    sq = rays_to(np.column_stack([rng.uniform(-1, 2, n), rng.uniform(-1, 1, n), np.full(n, 3.0)]),
+                 np.column_stack([rng.uniform(-0.6, 1.85, n), rng.uniform(-0.6, 0.6, n), np.full(n, -1.0)]))
+    g = _run(gsc, sq)
+    assert_gate(gate(g, osc.intersect(sq), sq, osc, 3.0, 8, label="squares"))
+    gid = ids_of(g)
+    assert (gid == 2).sum() > 0.25 * n and (gid == 5).sum() > 0.25 * n  # the Bezier and the Gregory square
+    # rays aimed at the segment and at the point: zero-volume leaf boxes, hit or missed by
+    # rounding on either side (excused as grazing); no disagreement may be anything else
+    tg = np.where(rng.uniform(size=(n, 1)) < 0.5, a + rng.uniform(0, 1, (n, 1)) * e, a + 0.5 * e)
+    dg = rays_to(np.column_stack([rng.uniform(2, 5, n), rng.uniform(-1, 1, n), np.full(n, 3.0)]), tg)
+    g = _run(gsc, dg)
+    assert np.isfinite(g[ids_of(g) != O.NO_HIT, 0]).all()
+    assert_gate(gate(g, osc.intersect(dg), dg, osc, 3.0, 8, min_match=0.0, label="collapsed"), min_match=0.0)
