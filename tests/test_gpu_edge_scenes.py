@@ -116,3 +116,22 @@ def test_collapsed_patches(ccs, local):
     g = _run(gsc, dg)
     assert np.isfinite(g[ids_of(g) != O.NO_HIT, 0]).all()
     assert_gate(gate(g, osc.intersect(dg), dg, osc, 3.0, 8, min_match=0.0, label="collapsed"), min_match=0.0)
+
+
+@pytest.mark.parametrize("local", [False, True], ids=["world", "local"])
+def test_negative_tmin_and_short_tmax(ccs, c1, local):
+    # hits behind the origin (tmin < 0) and intervals that end before the surface
+    rng = np.random.default_rng(11)
+    rays = np.concatenate([c1.primary[::4], c1.diffuse[::4]]).copy()
+    n = len(rays)
+    rays[:, 3] = -rng.uniform(0.0, 3.0, n).astype(np.float32)          # tmin in [-3, 0]
+    short = rng.uniform(size=n) < 0.3
+    rays[short, 7] = rng.uniform(0.0, 2.0, short.sum()).astype(np.float32)  # tmax in [0, 2]
+    gsc, osc = _both(ccs, c1.cp, c1.types, c1.leaf_depth, local)
+    g = _run(gsc, rays)
+    o = osc.intersect(rays)
+    assert_gate(gate(g, o, rays, osc, c1.diameter, c1.leaf_depth, label="tmin<0"))
+    hit = ids_of(g) != O.NO_HIT
+    t = g[hit, 0]
+    assert np.all(t >= rays[hit, 3]) and np.all(t <= rays[hit, 7])
+    assert (t < 0).sum() > 100  # some hits lie behind the origin
