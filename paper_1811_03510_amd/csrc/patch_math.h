@@ -63,20 +63,29 @@ struct SlabPair {
 };
 
 // Splits component g, folds its child intervals [lo, hi + d] into s, and returns
-// the seven points of every row.
+// the seven points of every row.  Each half's bounds over its 16 points are
+// linear chains of two-value steps, which the compiler folds into one
+// three-operand min / max per two points (min and max are exact, so the order
+// does not change the bounds).
 __device__ __forceinline__ void split_fold(const float g[4][4], float o, float inv, float d, Row7 e[4], SlabPair& s) {
 #pragma unroll
   for (int b = 0; b < 4; ++b) e[b] = casteljau_half(g[0][b], g[1][b], g[2][b], g[3][b]);
-  float la = min4(e[0].v[0], e[0].v[1], e[0].v[2], e[0].v[3]);
-  float ha = max4(e[0].v[0], e[0].v[1], e[0].v[2], e[0].v[3]);
-  float lb = min4(e[0].v[3], e[0].v[4], e[0].v[5], e[0].v[6]);
-  float hb = max4(e[0].v[3], e[0].v[4], e[0].v[5], e[0].v[6]);
+  float la = fminf(e[0].v[0], e[0].v[1]), ha = fmaxf(e[0].v[0], e[0].v[1]);
+  float lb = fminf(e[0].v[3], e[0].v[4]), hb = fmaxf(e[0].v[3], e[0].v[4]);
+  la = fminf(fminf(la, e[0].v[2]), e[0].v[3]);
+  ha = fmaxf(fmaxf(ha, e[0].v[2]), e[0].v[3]);
+  lb = fminf(fminf(lb, e[0].v[5]), e[0].v[6]);
+  hb = fmaxf(fmaxf(hb, e[0].v[5]), e[0].v[6]);
 #pragma unroll
   for (int b = 1; b < 4; ++b) {
-    la = fminf(la, min4(e[b].v[0], e[b].v[1], e[b].v[2], e[b].v[3]));
-    ha = fmaxf(ha, max4(e[b].v[0], e[b].v[1], e[b].v[2], e[b].v[3]));
-    lb = fminf(lb, min4(e[b].v[3], e[b].v[4], e[b].v[5], e[b].v[6]));
-    hb = fmaxf(hb, max4(e[b].v[3], e[b].v[4], e[b].v[5], e[b].v[6]));
+    la = fminf(fminf(la, e[b].v[0]), e[b].v[1]);
+    la = fminf(fminf(la, e[b].v[2]), e[b].v[3]);
+    ha = fmaxf(fmaxf(ha, e[b].v[0]), e[b].v[1]);
+    ha = fmaxf(fmaxf(ha, e[b].v[2]), e[b].v[3]);
+    lb = fminf(fminf(lb, e[b].v[3]), e[b].v[4]);
+    lb = fminf(fminf(lb, e[b].v[5]), e[b].v[6]);
+    hb = fmaxf(fmaxf(hb, e[b].v[3]), e[b].v[4]);
+    hb = fmaxf(fmaxf(hb, e[b].v[5]), e[b].v[6]);
   }
   const float a0 = (la - o) * inv, a1 = (ha + d - o) * inv;
   const float b0 = (lb - o) * inv, b1 = (hb + d - o) * inv;
