@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   int depth = 0;
   uint32_t vpref = 0;  // learned order: bit 0 set = take the v-half in bit 1 at the next split
   float pad2 = 0.0f;   // patch-local frames: twice the current patch's box pad (added to d)
+  float pix = 0.0f, piy = 0.0f, piz = 0.0f;  // reciprocal direction in the current patch's frame
 
   for (;;) {
     if (__ballot(mode != kDead) == 0) break;
@@ -201,16 +202,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           const float4 meta = reinterpret_cast<const float4*>(rec)[15];
           pmeta = __float_as_uint(meta.w);
           if (s.frames) {
-            // patch-local frame: origin and direction mapped by the patch's rows; the
-            // reciprocals hold the mapped direction until the lane leaves the patch
+            // patch-local frame: origin and direction mapped by the patch's rows
             const float4* fr = s.frames + (size_t)bt.frame[batch_of(bt, rid)] * s.frame_frames_f4 + 3 * (size_t)rec_idx;
             const float4 r0 = fr[0], r1 = fr[1], r2 = fr[2];
             float pdx, pdy, pdz;
             patch_frame_rows(meta, r0, r1, r2, wr.ox, wr.oy, wr.oz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane],
                              wr.tmin, pox, poy, poz, pdx, pdy, pdz, ptmin, pt0);
-            wr.ix = safe_inv(pdx);
-            wr.iy = safe_inv(pdy);
-            wr.iz = safe_inv(pdz);
+            pix = safe_inv(pdx);
+            piy = safe_inv(pdy);
+            piz = safe_inv(pdz);
             // boxes grown by the pad on all sides: the low planes move by -pad through the
             // origin (o + pad), the high planes by +pad through d + 2 pad
             pox += r0.w;
@@ -220,6 +220,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           } else {
             patch_frame(meta, wr.ox, wr.oy, wr.oz, s_dir[0][lane], s_dir[1][lane], s_dir[2][lane], wr.tmin, pox,
                         poy, poz, ptmin, pt0);
+            pix = wr.ix;
+            piy = wr.iy;
+            piz = wr.iz;
           }
           code = trail = mirror = 0;
           depth = 0;
@@ -352,9 +355,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (mode == kDecide) {
           // inputs of the node one level up (the u-split just taken), with the direction in
           // the frame the patch is subdivided in
-          const float fdx = s.frames ? 1.0f / wr.ix : s_dir[0][lane];
-          const float fdy = s.frames ? 1.0f / wr.iy : s_dir[1][lane];
-          const float fdz = s.frames ? 1.0f / wr.iz : s_dir[2][lane];
+          const float fdx = s.frames ? 1.0f / pix : s_dir[0][lane];
+          const float fdy = s.frames ? 1.0f / piy : s_dir[1][lane];
+          const float fdz = s.frames ? 1.0f / piz : s_dir[2][lane];
           float f[16];
           policy_features(policy_load_node(s_feat, lane, s_mirror[lane]), pox, poy, poz, fdx, fdy, fdz, depth - 1,
                           s.leaf_depth, (pmeta & kGregoryBit) != 0, f);
@@ -383,9 +386,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       // split each component and fold its two child boxes into the slab test at once
       Row7 ex[4], ey[4], ez[4];
       SlabPair sp2 = {ptmin, __builtin_inff(), ptmin, __builtin_inff()};
-      split_fold(G.x, pox, wr.ix, dx, ex, sp2);
-      split_fold(G.y, poy, wr.iy, dy, ey, sp2);
-      split_fold(G.z, poz, wr.iz, dz, ez, sp2);
+      split_fold(G.x, pox, pix, dx, ex, sp2);
+      split_fold(G.y, poy, piy, dy, ey, sp2);
+      split_fold(G.z, poz, piz, dz, ez, sp2);
       // the best distance in the patch frame: best_t - pt0 carries the rounding of
       // best_t = pt0 + t and of the difference (each at most 2^-24 relative), so it
       // is widened by twice their bound and a leaf at the best distance is never pruned
@@ -456,11 +459,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
           mode = kGrid;
           if (kStats) cnt.backtrack++;
         } else {
-          if (s.frames) {  // patch done: world reciprocals back for the traversal
-            wr.ix = safe_inv(s_dir[0][lane]);
-            wr.iy = safe_inv(s_dir[1][lane]);
-            wr.iz = safe_inv(s_dir[2][lane]);
-          }
           if (sp > 0) {  // next candidate from the stack
             --sp;
             cur = stack[sp * kBlock + lane];
