@@ -114,28 +114,33 @@ struct RayP {  // a ray in some frame: origin, reciprocal direction, tmin
   float tmin;
 };
 
-// 1 + 2*gamma_3 with gamma_n = n u / (1 - n u), u = 2^-24: widening the far
-// distance by it makes the fp32 slab test conservative against the rounding
-// of the plane distances (robust BVH traversal of Ize 2013, cited in Sec. 3.4).
-// The distances are formed as (plane - o) * (1/d): two roundings, each relative
-// to the distance itself, which is what the widening covers (a precomputed
-// -o/d would carry an error relative to |o|/|d|, not to the distance).
-constexpr float kFarScale = 1.0f + 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);
+// Widening of the far distance that makes the fp32 slab test conservative
+// against rounding (robust BVH traversal of Ize 2013, cited in Sec. 3.4).  A
+// distance is formed as (plane - o) * (1/d): the difference and the product are
+// rounded once each (u = 2^-24 relative), and 1/d comes from the hardware
+// reciprocal, within 1 ulp (2u relative), so each distance carries at most
+// gamma_4 = 4u / (1 - 4u) of relative error and an entry can exceed its exit by
+// rounding alone by 2 gamma_4 of the exit's magnitude.  (A precomputed -o/d
+// would carry an error relative to |o|/|d|, not to the distance.)
+// kFarScale = 1 + 5 * 2^-23, the first fp32 value above 1 + 2 gamma_4.
+constexpr float kFarScale = 1.0f + 5.0f * 1.1920929e-7f;
 // The same widening for a negative far distance (patch-frame distances are measured
 // from the ray's point closest to the patch anchor, so a box the ray leaves before
-// that point has a negative far distance): 1 - 2 (kFarScale - 1), at least 2 gamma_3
-// below 1 after rounding.
-constexpr float kFarShrink = 1.0f - 2.0f * (kFarScale - 1.0f);
+// that point has a negative far distance): 1 - 10 * 2^-24, below 1 - 2 gamma_4.
+constexpr float kFarShrink = 1.0f - 10.0f * 5.9604645e-8f;
 
-// A far distance moved outwards by 2 gamma_3 of its magnitude, whatever its sign
+// A far distance moved outwards by 2 gamma_4 of its magnitude, whatever its sign
 // (a plain product by kFarScale would pull a negative one inwards, and a box of zero
 // thickness, where entry equals exit, would then be missed).
 __device__ __forceinline__ float widen_far(float f) { return f * (f >= 0.0f ? kFarScale : kFarShrink); }
 
+// Reciprocal of a direction component from the hardware reciprocal (within
+// 1 ulp), branch-free; a zero component gets a huge finite reciprocal, so that the
+// slab of that axis is unbounded for origins between the planes and empty
+// otherwise, without 0 * inf.
 __device__ __forceinline__ float safe_inv(float d) {
-  // a zero component gets a huge finite reciprocal: the slab of that axis is then
-  // unbounded for origins between the planes and empty otherwise, without 0*inf
-  return d == 0.0f ? copysignf(1e30f, d) : __frcp_rn(d);
+  const float r = __builtin_amdgcn_rcpf(d);
+  return d == 0.0f ? copysignf(1e30f, d) : r;
 }
 
 // Patch frame of a ray: anchored at the patch's anchor, origin moved along the
