@@ -199,7 +199,7 @@ typedef struct ccs_launch_params {
 } ccs_launch_params;
 
 /* Sets the launch configuration used by later ccs_intersect* calls on the
- * scene.  Defaults: {0, 16, 1, 16, 2, 8}.  CCS_ERR_INVALID_ARG for thresholds
+ * scene.  Defaults: {0, 16, 1, 8, 3, 8}.  CCS_ERR_INVALID_ARG for thresholds
  * outside [1, 64].  Not synchronized with calls in flight on other threads. */
 ccs_status ccs_scene_set_launch(ccs_scene* scene, const ccs_launch_params* params);
 

@@ -26,7 +26,7 @@ import os
 import statistics
 from pathlib import Path
 
-DEFAULT = dict(waves_per_cu=0, fetch_min=16, traverse_min=1, grid_min=16, traverse_steps=2, decide_min=8)
+DEFAULT = dict(waves_per_cu=0, fetch_min=16, traverse_min=1, grid_min=8, traverse_steps=3, decide_min=8)
 SPACE = dict(
     waves_per_cu=[0, 4, 8],
     fetch_min=[4, 8, 16, 24, 32, 48],
@@ -96,10 +96,19 @@ def confirm(scene, batches, cands: list, rounds: int = 5, log=None) -> tuple[dic
     return dict(cands[k]), med[k]
 
 
-def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None,
+# Settings that won on the benchmark workloads, always timed in the confirmation
+# round (a descent step can miss one when a timing is noisy).
+PRESETS = (
+    dict(DEFAULT, fetch_min=16, traverse_min=1, grid_min=16, traverse_steps=2),
+    dict(DEFAULT, fetch_min=16, traverse_min=2, grid_min=4, traverse_steps=3),
+    dict(DEFAULT, fetch_min=24, traverse_min=8, grid_min=16, traverse_steps=4),
+)
+
+
+def tune(scene, batches, reps: int = 5, sweeps: int = 2, log=None, space=None,
          learned: bool = False, finalists: int = 4) -> tuple[dict, float, list]:
     """Coordinate descent over ``space`` from DEFAULT, then the ``finalists``
-    fastest settings seen (and DEFAULT) timed again side by side (confirm).
+    fastest settings seen, DEFAULT and PRESETS timed again side by side (confirm).
     Returns (params, ms, trials)."""
     space = dict(space or SPACE)
     if not learned:
@@ -132,9 +141,10 @@ def tune(scene, batches, reps: int = 3, sweeps: int = 2, log=None, space=None,
     if finalists > 1:
         ranked = sorted(seen.items(), key=lambda kv: kv[1])[:finalists]
         cands = [dict(k) for k, _ in ranked]
-        if dict(DEFAULT) not in cands:
-            cands.append(dict(DEFAULT))
-        best, best_ms = confirm(scene, batches, cands, log=log)
+        for extra in (dict(DEFAULT),) + tuple(dict(p) for p in PRESETS):
+            if extra not in cands:
+                cands.append(extra)
+        best, best_ms = confirm(scene, batches, cands, rounds=7, log=log)
     scene.set_launch(**best)
     return best, best_ms, trials
 

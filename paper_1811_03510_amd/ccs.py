@@ -206,8 +206,8 @@ class Scene:
         _check(lib().ccs_intersect_batched(self._h, arr, len(batches), _stream(stream)))
         return out
 
-    def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 1, grid_min: int = 16,
-                   traverse_steps: int = 2, decide_min: int = 8):
+    def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 1, grid_min: int = 8,
+                   traverse_steps: int = 3, decide_min: int = 8):
         p = LaunchParams(waves_per_cu, fetch_min, traverse_min, grid_min, traverse_steps, decide_min)
         _check(lib().ccs_scene_set_launch(self._h, C.byref(p)))
 

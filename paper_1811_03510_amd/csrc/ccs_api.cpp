@@ -93,7 +93,7 @@ struct ccs_scene {
   std::vector<uint32_t> level_offsets;  // nodes of depth d: level_nodes[level_offsets[d] .. level_offsets[d+1])
   uint32_t* queues = nullptr;  // kQueueSlots ray-queue counters
   std::atomic<uint32_t> next_queue{0};
-  ccs_launch_params launch{0, 16, 1, 16, 2, 8};
+  ccs_launch_params launch{0, 16, 1, 8, 3, 8};
   uint2* policy_w = nullptr;   // packed network fragments, allocated on first use
   float4* policy_b = nullptr;
   std::vector<std::pair<void*, size_t>> allocations;  // device buffers and their sizes

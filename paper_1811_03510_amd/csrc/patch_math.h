@@ -174,12 +174,13 @@ __device__ __forceinline__ void patch_frame_rows(float4 anchor, float4 r0, float
   const double ax = fma((double)t0, (double)dx, (double)ox - (double)anchor.x);
   const double ay = fma((double)t0, (double)dy, (double)oy - (double)anchor.y);
   const double az = fma((double)t0, (double)dz, (double)oz - (double)anchor.z);
-  pox = (float)((double)r0.x * ax + (double)r0.y * ay + (double)r0.z * az);
-  poy = (float)((double)r1.x * ax + (double)r1.y * ay + (double)r1.z * az);
-  poz = (float)((double)r2.x * ax + (double)r2.y * ay + (double)r2.z * az);
-  pdx = (float)((double)r0.x * dx + (double)r0.y * dy + (double)r0.z * dz);
-  pdy = (float)((double)r1.x * dx + (double)r1.y * dy + (double)r1.z * dz);
-  pdz = (float)((double)r2.x * dx + (double)r2.y * dy + (double)r2.z * dz);
+  const double ex = dx, ey = dy, ez = dz;
+  pox = (float)fma((double)r0.z, az, fma((double)r0.y, ay, (double)r0.x * ax));
+  poy = (float)fma((double)r1.z, az, fma((double)r1.y, ay, (double)r1.x * ax));
+  poz = (float)fma((double)r2.z, az, fma((double)r2.y, ay, (double)r2.x * ax));
+  pdx = (float)fma((double)r0.z, ez, fma((double)r0.y, ey, (double)r0.x * ex));
+  pdy = (float)fma((double)r1.z, ez, fma((double)r1.y, ey, (double)r1.x * ex));
+  pdz = (float)fma((double)r2.z, ez, fma((double)r2.y, ey, (double)r2.x * ex));
   ptmin = (float)((double)tmin - (double)t0);
 }
 

@@ -284,18 +284,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       const uint32_t n_own = n_wait < kGridOwners ? n_wait : kGridOwners;
       const uint32_t rank = (uint32_t)__popcll(mg & ((1ull << lane) - 1ull));
       const bool owner = mode == kGrid && rank < n_own;
-      const uint32_t hr = (uint32_t)lane / 3u, hc = (uint32_t)lane - 3u * hr;
-      const bool helper = hr < n_own;
+      // lanes past the helpers compute owner 0's grid again (the instructions run for the
+      // whole wave anyway; their results are never pulled)
+      const uint32_t hr0 = (uint32_t)lane / 3u, hc = (uint32_t)lane - 3u * hr0;
+      const uint32_t hr = hr0 < n_own ? hr0 : 0u;
       // the owner's record, path code, depth and type, read by its helpers
-      const int from = (int)nth_set_bit(mg, helper ? hr : 0u) * 4;
+      const int from = (int)nth_set_bit(mg, hr) * 4;
       const uint64_t rp = reinterpret_cast<uint64_t>(recs + (size_t)rec_idx * kRecFloats);
       const uint32_t dg = (uint32_t)depth | ((pmeta & kGregoryBit) ? 0x100u : 0u);
       const uint32_t h_lo = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)rp);
       const uint32_t h_hi = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(rp >> 32));
       const uint32_t h_code = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)code);
       const uint32_t h_dg = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)dg);
-      float qo[4][4], dc = 0.0f;
-      if (helper) {
+      float qo[4][4], dc;
+      {
         const float* hrec = reinterpret_cast<const float*>(((uint64_t)h_hi << 32) | h_lo);
         const int hd = (int)(h_dg & 0xFFu);
         // domain of the node at depth hd: position from the path code, sizes from the depth
@@ -306,11 +308,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         float q[4][4];
         calc_component(hrec + 16 * hc, hrec + 48 + 4 * hc, (h_dg & 0x100u) != 0, u0, u0 + su, v0, v0 + sv, q, dc);
         orient(q, (hd & 1) != 0, qo);
-      } else {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) qo[a][b] = 0.0f;
       }
       const int to = owner ? (int)(12u * rank) : 0;  // byte index of the owner's x helper
 #pragma unroll
