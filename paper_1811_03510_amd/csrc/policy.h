@@ -103,13 +103,16 @@ __device__ __forceinline__ PolicyRaw policy_raw(const float sx[4], const float s
 __device__ __forceinline__ void policy_features(const PolicyRaw& r, float ox, float oy, float oz, float dx,
                                                 float dy, float dz, int depth, int leaf_depth, bool gregory,
                                                 float f[16]) {
+  // the inputs end as bfloat16 (8 significant bits): the hardware square root and
+  // reciprocals (within 1 ulp of fp32) are ample, and the training records are
+  // formed by this same code
   const float t_in = fminf(r.n_lo, r.n_up);
-  const float dl = __fsqrt_rn(dx * dx + dy * dy + dz * dz);
-  const float il = 1.0f / dl;
+  const float dl = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+  const float il = __builtin_amdgcn_rcpf(dl);
   const float nx = dx * il, ny = dy * il, nz = dz * il;
   // Duff et al. 2017, branch-free orthonormal basis around n
   const float sg = copysignf(1.0f, nz);
-  const float a = -1.0f / (sg + nz);
+  const float a = -__builtin_amdgcn_rcpf(sg + nz);
   const float b = nx * ny * a;
   const float e1x = 1.0f + sg * nx * nx * a, e1y = sg * b, e1z = -sg * nx;
   const float e2x = b, e2y = sg + ny * ny * a, e2z = -ny;
@@ -124,13 +127,13 @@ __device__ __forceinline__ void policy_features(const PolicyRaw& r, float ox, fl
     s = fmaxf(s, fmaxf(fabsf(f[3 * k]), fmaxf(fabsf(f[3 * k + 1]), fabsf(f[3 * k + 2]))));
   }
   s = fmaxf(s, 1e-30f);
-  const float is = 1.0f / s;
+  const float is = __builtin_amdgcn_rcpf(s);
 #pragma unroll
   for (int k = 0; k < 12; ++k) f[k] *= is;
   const float sc = dl * is;
   f[12] = fminf(fmaxf((r.n_lo - r.n_up) * sc, -4.0f), 4.0f) * 0.25f;
   f[13] = fminf(fmaxf((r.x_lo - r.x_up) * sc, -4.0f), 4.0f) * 0.25f;
-  f[14] = (float)depth / (float)(2 * leaf_depth);
+  f[14] = (float)depth * __builtin_amdgcn_rcpf((float)(2 * leaf_depth));
   f[15] = gregory ? 1.0f : 0.0f;
 }
 

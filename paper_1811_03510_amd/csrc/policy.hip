@@ -80,8 +80,8 @@ __global__ __launch_bounds__(64) void k_record(DeviceScene s, const ccs_ray* __r
       const float sx[4] = {qx[0][0], qx[3][0], qx[0][3], qx[3][3]};
       const float sy[4] = {qy[0][0], qy[3][0], qy[0][3], qy[3][3]};
       const float sz[4] = {qz[0][0], qz[3][0], qz[0][3], qz[3][3]};
-      const float fdx = s.frames ? 1.0f / ix : rd.x, fdy = s.frames ? 1.0f / iy : rd.y,
-                  fdz = s.frames ? 1.0f / iz : rd.z;
+      const float fdx = s.frames ? __builtin_amdgcn_rcpf(ix) : rd.x, fdy = s.frames ? __builtin_amdgcn_rcpf(iy) : rd.y,
+                  fdz = s.frames ? __builtin_amdgcn_rcpf(iz) : rd.z;
       policy_features(policy_raw(sx, sy, sz, 0u, sp), pox, poy, poz, fdx, fdy, fdz, (int)(2 * k), (int)L, greg, f);
       label = 2u * ((iu >> (L - 1 - k)) & 1u) + ((iv >> (L - 1 - k)) & 1u);
     }

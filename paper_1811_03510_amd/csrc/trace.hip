@@ -352,9 +352,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         if (mode == kDecide) {
           // inputs of the node one level up (the u-split just taken), with the direction in
           // the frame the patch is subdivided in
-          const float fdx = s.frames ? 1.0f / pix : s_dir[0][lane];
-          const float fdy = s.frames ? 1.0f / piy : s_dir[1][lane];
-          const float fdz = s.frames ? 1.0f / piz : s_dir[2][lane];
+          const float fdx = s.frames ? __builtin_amdgcn_rcpf(pix) : s_dir[0][lane];
+          const float fdy = s.frames ? __builtin_amdgcn_rcpf(piy) : s_dir[1][lane];
+          const float fdz = s.frames ? __builtin_amdgcn_rcpf(piz) : s_dir[2][lane];
           float f[16];
           policy_features(policy_load_node(s_feat, lane, s_mirror[lane]), pox, poy, poz, fdx, fdy, fdz, depth - 1,
                           s.leaf_depth, (pmeta & kGregoryBit) != 0, f);
