@@ -36,7 +36,7 @@ METRIC = "MRays/s primary+diffuse at 1M patches: plain vs learned-order batched,
 # vector operations the arithmetic needs (add, sub, mul, fma, 2- or 3-operand
 # min/max, compare, select, bit op, and the midpoint (a+b)/2 as one add with the
 # /2 output modifier: 1 each; a division: 1).  Derived from the method's
-# arithmetic, not from the compiled code; the derivation is in the design doc.
+# arithmetic, not from the compiled code; each entry below names its parts.
 OPS_PER_UNIT = {
     "ray": 25,         # ray setup (validity, reciprocals) and the hit write
     "node": 58,        # BVH node: two slab tests (25 each), ordering, stack push
@@ -174,7 +174,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU: every ray is independent, so N GPUs "
+        print(json.dumps({"error": "the benchmark runs on one GPU: every ray is independent, so N GPUs "
                                    "would each run this same benchmark on 1/N of the rays; use --gpus 1"}))
         sys.exit(2)
 

@@ -65,7 +65,7 @@ typedef enum ccs_status {
   CCS_ERR_INVALID_ARG = 1, /* null pointer, bad tag, L out of range, non-finite input, size mismatch */
   CCS_ERR_OOM = 2,         /* device or host allocation failed, or refused by CCS_MAX_DEVICE_BYTES */
   CCS_ERR_HIP = 3,         /* a HIP runtime call failed; see ccs_last_error() */
-  CCS_ERR_UNSUPPORTED = 4  /* no gfx950 device, or a flag this build does not support */
+  CCS_ERR_UNSUPPORTED = 4  /* no gfx950 device, an unknown flag, or a BVH too deep for a kernel's stack */
 } ccs_status;
 
 typedef enum ccs_patch_type { CCS_BEZIER = 0, CCS_GREGORY = 1 } ccs_patch_type;
