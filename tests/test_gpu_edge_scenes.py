@@ -135,3 +135,17 @@ def test_negative_tmin_and_short_tmax(ccs, c1, local):
     t = g[hit, 0]
     assert np.all(t >= rays[hit, 3]) and np.all(t <= rays[hit, 7])
     assert (t < 0).sum() > 100  # some hits lie behind the origin
+
+
+@pytest.mark.parametrize("scale", [1e-12, 1e12])
+def test_direction_magnitude(ccs, c1, scale):
+    # t is measured in units of the given direction: scaling d by k scales t by 1/k and
+    # leaves the patch and (u, v) alone, through reciprocals up to 1e12 and down to 1e-12
+    rays = np.concatenate([c1.primary[::8], c1.diffuse[::8]]).copy()
+    rays[:, 4:7] = (rays[:, 4:7].astype(np.float64) * scale).astype(np.float32)
+    gsc, osc = _both(ccs, c1.cp, c1.types, c1.leaf_depth, True)
+    g = _run(gsc, rays)
+    o = osc.intersect(rays)
+    assert_gate(gate(g, o, rays, osc, c1.diameter / scale, c1.leaf_depth, label=f"|d| x {scale:g}"))
+    hit = ids_of(g) != O.NO_HIT
+    assert hit.sum() > 1000 and np.isfinite(g[hit]).all()
