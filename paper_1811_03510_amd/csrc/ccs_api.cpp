@@ -124,8 +124,14 @@ void dev_free(ccs_scene* s, void* p) {
     }
 }
 
+// Also used on the error paths of scene creation, where an upload or the frame
+// refit may still be queued: the device is drained before the memory goes.
 void free_scene(ccs_scene* s) {
   if (!s) return;
+  if (!s->allocations.empty()) {
+    (void)hipDeviceSynchronize();
+    (void)hipGetLastError();
+  }
   for (const auto& a : s->allocations) raw_free(a.first, a.second);
   delete s;
 }
@@ -163,10 +169,15 @@ ccs_status check_finite(const float* cp, size_t count) {
 
 namespace {
 
-// Device scratch owned by one synchronous call, freed on every return path.
+// Device scratch owned by one synchronous call, freed on every return path.  An
+// error return can leave launches of the call queued that still read it, so the
+// device is drained before the memory is released.
 struct Scratch {
   std::vector<std::pair<void*, size_t>> p;
   ~Scratch() {
+    if (p.empty()) return;
+    (void)hipDeviceSynchronize();
+    (void)hipGetLastError();
     for (const auto& q : p) raw_free(q.first, q.second);
   }
   template <class T>
@@ -760,10 +771,6 @@ ccs_status ccs_scene_info_get(const ccs_scene* s, ccs_scene_info* info) {
   return CCS_OK;
 }
 
-void ccs_scene_destroy(ccs_scene* s) {
-  if (!s) return;
-  (void)hipDeviceSynchronize();
-  free_scene(s);
-}
+void ccs_scene_destroy(ccs_scene* s) { free_scene(s); }  // drains the device first
 
 }  // extern "C"
