@@ -450,6 +450,11 @@ def main():
                 head = "batched" if "batched" in variants else "plain"  # a failing variant reports nothing
                 ms_step, value = variants[head]["ms_per_step"], variants[head]["mrays_per_s"]
         log(f"cpu baseline: {cpu['value']} MRays/s on {threads} threads; parity {parity}")
+        if not (rp["ok"] and rd["ok"]):
+            # the closest-first hits are the batched and plain variants' (bit-identical):
+            # no timed variant is oracle-exact then, and the line says so
+            print(f"bench: PARITY FAILED on the oracle sample: primary {rp['excused']}, diffuse {rd['excused']}, "
+                  f"hard examples {rp['hard'] + rd['hard']}", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -477,6 +482,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
+        "parity_ok": None if parity is None else bool(all(c["ok"] for c in parity.values())),
         "work_per_ray": work,
         "scene": {"create_s": round(create_s, 3), "bvh_build_s": round(info["build_seconds"], 3),
                   "bvh_depth": info["bvh_depth"], "device_mib": round(info["device_bytes"] / 2**20, 1)},

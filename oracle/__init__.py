@@ -53,6 +53,7 @@ def lib():
         L.orc_leaf_entry.argtypes = [vp, u32, P(C.c_float), u32, u32]
         L.orc_leaf_entry.restype = d
         L.orc_domain_box.argtypes = [vp, u32, u32, u32, u32, u32, P(d)]
+        L.orc_leaf_box_alg3.argtypes = [vp, u32, u32, u32, P(d)]
         _lib = L
     return _lib
 
@@ -200,11 +201,9 @@ class Scene:
         return out
 
     def leaf_entry(self, patch, ray8, u, v):
-        """Entry distance into the box of the leaf containing (u, v) (inf if missed)."""
+        """Entry distance into the Alg. 3 box of the leaf containing (u, v) (inf if missed)."""
         r = np.ascontiguousarray(ray8, dtype=np.float32).reshape(8)
-        leaf = (1 << 23) >> self.leaf_depth
-        pu = min(int(np.floor(u * 2.0 ** 23)) & ~(leaf - 1), (1 << 23) - leaf)
-        pv = min(int(np.floor(v * 2.0 ** 23)) & ~(leaf - 1), (1 << 23) - leaf)
+        _, pu, pv = self._leaf_corner(u, v)
         return lib().orc_leaf_entry(self._h, int(patch), _p(r, C.c_float), pu, pv)
 
     def domain_box(self, patch, u0, v0, size_u, size_v):
@@ -214,8 +213,21 @@ class Scene:
                              _p(box, C.c_double))
         return box[:3], box[3:]
 
-    def leaf_box(self, patch, u, v):
+    def _leaf_corner(self, u, v):
         leaf = (1 << 23) >> self.leaf_depth
         pu = min(int(np.floor(u * 2.0 ** 23)) & ~(leaf - 1), (1 << 23) - leaf)
         pv = min(int(np.floor(v * 2.0 ** 23)) & ~(leaf - 1), (1 << 23) - leaf)
+        return leaf, pu, pv
+
+    def leaf_box(self, patch, u, v):
+        """[lo, hi] of the leaf containing (u, v) bounded on its own domain (calcPointsAndD)."""
+        leaf, pu, pv = self._leaf_corner(u, v)
         return self.domain_box(patch, pu, pv, leaf, leaf)
+
+    def leaf_box_alg3(self, patch, u, v):
+        """[lo, hi] of the leaf containing (u, v) as Alg. 3 tests it: its half of the
+        parent's grid, grown by the parent's displacement."""
+        _, pu, pv = self._leaf_corner(u, v)
+        box = np.zeros(6)
+        lib().orc_leaf_box_alg3(self._h, int(patch), pu, pv, _p(box, C.c_double))
+        return box[:3], box[3:]

@@ -1131,25 +1131,38 @@ int orc_trace_patch_alg3(void* s, uint32_t patch, const float* ray8, double cap,
   return steps;
 }
 
-// Entry distance of a ray into the box of the leaf at (pu, pv) (units 2^-23) as
-// the method forms it: its parent's lower grid (crop, or calcPointsAndD for a
-// Gregory patch), split at 1/2 along v, the half extended by the parent's d.
-// Ancestors are not tested.  Returns +inf when the box is missed.
-double orc_leaf_entry(void* s, uint32_t patch, const float* ray8, uint32_t pu, uint32_t pv) {
-  const Scene& S = *(Scene*)s;
+// Box of the leaf at (pu, pv) (units 2^-23) as the method forms it (Alg. 3): its
+// parent's lower grid (crop, or calcPointsAndD for a Gregory patch) split at 1/2
+// along v, the last axis, the leaf's half extended by the parent's d, in the frame
+// subdivision uses.
+static void alg3_leaf_box(const Scene& S, uint32_t patch, uint32_t pu, uint32_t pv, V3* lo, V3* hi) {
   const Patch& P = work_patch(S, patch);
-  Ray r = work_ray(S, patch, load_ray(ray8));
   const uint32_t leaf = kFull >> S.L;
   uint32_t ppv = pv & ~(2 * leaf - 1);
   Bound b = calc_points_and_d_int(P, pu, ppv, leaf, 2 * leaf);
   Grid gl, gr;
   split_half(b.q, 1, &gl, &gr);
+  grid_box((pv & leaf) ? gr : gl, b.d, P.pad, lo, hi);
+}
+
+// Entry distance of a ray into that box; ancestors are not tested.  Returns +inf
+// when the box is missed.
+double orc_leaf_entry(void* s, uint32_t patch, const float* ray8, uint32_t pu, uint32_t pv) {
+  const Scene& S = *(Scene*)s;
+  Ray r = work_ray(S, patch, load_ray(ray8));
   V3 lo, hi;
-  grid_box((pv & leaf) ? gr : gl, b.d, P.pad, &lo, &hi);
+  alg3_leaf_box(S, patch, pu, pv, &lo, &hi);
   double e;
   if (!ray_valid(r) || !slab(r, lo, hi, std::numeric_limits<double>::infinity(), &e))
     return std::numeric_limits<double>::infinity();
   return e;
+}
+
+// The same box as [lo, hi] (6 doubles).
+void orc_leaf_box_alg3(void* s, uint32_t patch, uint32_t pu, uint32_t pv, double* box6) {
+  V3 lo, hi;
+  alg3_leaf_box(*(const Scene*)s, patch, pu, pv, &lo, &hi);
+  box6[0] = lo.x; box6[1] = lo.y; box6[2] = lo.z; box6[3] = hi.x; box6[4] = hi.y; box6[5] = hi.z;
 }
 
 // Box [lo, hi] (6 doubles) of a domain's lower grid plus displacement

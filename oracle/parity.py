@@ -10,9 +10,11 @@ excused only when the paper's error model explains it:
   * seam  -- different patches: the two hit points are within 1e-4 D of each
              other, or a reported (u, v) lies within 2^-L of its patch boundary
              (shared edges); a different leaf of the same patch is never a seam;
-  * graze -- the ray only clips the leaf box the side that hit reported: its path
-             inside that box is shorter than 1e-3 of the box diagonal (plus
-             1e-6 (t + 1) of rounding): silhouettes, box edges and corners;
+  * graze -- the ray only clips the leaf box the side that hit reported (the box
+             Alg. 3 tests, the leaf's half of its parent's grid with the parent's
+             displacement, or the leaf's own bound): its path inside that box is
+             shorter than 1e-3 of the box diagonal (plus 1e-6 (t + 1) of
+             rounding): silhouettes, box edges and corners;
   * tangent -- same patch, |dt| within tolerance, the ray within 1.2 degrees of
              tangent to the surface at the oracle's hit (|cos| < 0.02), and the
              surface at the GPU's (u, v) within the GPU leaf box's diagonal of the
@@ -109,16 +111,19 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
                 if dist <= np.linalg.norm(hi - lo) + 1e-6 * (abs(gt[k]) + 1.0):
                     kind = "tangent"
         if kind == "hard":
-            # the side that hit: does the ray merely clip its leaf box?  (The box is in
-            # the patch's frame, where the ray is taken too.)
+            # the side that hit: does the ray merely clip its leaf box, the box Alg. 3
+            # tests (the half of the parent's grid grown by the parent's displacement)
+            # or the leaf's own bound?  (Boxes are in the patch's frame, where the ray
+            # is taken too.)
             for side_hit, pid, u, v, t in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k], ora["t"][k]),
                                            (g_hit[k], gid[k], gpu[k, 2], gpu[k, 3], gt[k])):
-                if side_hit:
-                    lo, hi = osc.leaf_box(pid, u, v)
-                    slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-6 * (abs(t) + 1.0)
-                    if abs(_path_in_box(_in_frame(osc, pid, ray), lo, hi)) <= slack:
-                        kind = "graze"
-                        break
+                if side_hit and kind == "hard":
+                    rf = _in_frame(osc, pid, ray)
+                    for lo, hi in (osc.leaf_box_alg3(pid, u, v), osc.leaf_box(pid, u, v)):
+                        slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-6 * (abs(t) + 1.0)
+                        if abs(_path_in_box(rf, lo, hi)) <= slack:
+                            kind = "graze"
+                            break
         kinds[kind] += 1
         if kind == "hard" and len(hard) < 10:
             hard.append(dict(ray=int(k), gpu=(float(gt[k]), int(gid[k]), float(gpu[k, 2]), float(gpu[k, 3])),

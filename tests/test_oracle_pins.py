@@ -291,6 +291,53 @@ def test_boxes_are_conservative_and_bezier_boxes_nest(c1):
                     assert np.all(clo >= lo - 1e-15 * ext) and np.all(chi <= hi + 1e-15 * ext)
 
 
+def test_alg3_leaf_box_bounds_its_leaf(c1, c1_oracle):
+    """The box a leaf is recorded by (Alg. 3: its half of the parent's lower grid,
+    grown by the parent's displacement) bounds the surface over the leaf's domain
+    (Sec. 3.2); for a Bezier patch it is the leaf's own crop box (split halves are
+    crops, Alg. 1), and leaf_entry is finite exactly when a slab test of the box hits."""
+    from oracle.parity import _path_in_box
+    rng = np.random.default_rng(17)
+    L = c1.leaf_depth
+    n = 2 ** L
+    loc = O.Scene(c1.cp, c1.types, L, local_frames=True)
+    idx = np.concatenate([np.where(c1.types == 1)[0][:8], np.where(c1.types == 0)[0][:4]])
+    for pid in idx:
+        cp = c1.cp[pid].astype(np.float64)
+        greg = bool(c1.types[pid])
+        ext = np.ptp(cp.reshape(-1, 3), axis=0).max()
+        R = loc.patch_frame(pid)
+        for _ in range(6):
+            iu, iv = rng.integers(0, n, 2)
+            uc, vc = (iu + 0.5) / n, (iv + 0.5) / n
+            for sc, rot in ((c1_oracle, np.eye(3)), (loc, R)):
+                lo, hi = sc.leaf_box_alg3(pid, uc, vc)
+                assert np.all(hi >= lo)
+                for s in np.linspace(0, 1, 9):
+                    for t in np.linspace(0, 1, 9):
+                        f = rot @ O.patch_eval(cp, greg, (iu + s) / n, (iv + t) / n)[0]
+                        assert np.all(f >= lo - 1e-12 * ext) and np.all(f <= hi + 1e-12 * ext)
+                if not greg:
+                    olo, ohi = sc.leaf_box(pid, uc, vc)
+                    assert np.allclose(lo, olo, rtol=0, atol=1e-12 * ext)
+                    assert np.allclose(hi, ohi, rtol=0, atol=1e-12 * ext)
+            # rays through the box's centre hit it; rays passing beside it miss
+            lo, hi = c1_oracle.leaf_box_alg3(pid, uc, vc)
+            c = 0.5 * (lo + hi)
+            for off, want in ((0.0, True), (1.5, False)):
+                d = rng.normal(size=3)
+                d /= np.linalg.norm(d)
+                side = np.cross(d, rng.normal(size=3))
+                side /= np.linalg.norm(side)
+                p = c + off * np.linalg.norm(hi - lo) * side
+                ray = np.array([*(p - 2.0 * d), 0.0, *d, np.inf], np.float32)
+                e = c1_oracle.leaf_entry(pid, ray, uc, vc)
+                assert np.isfinite(e) == want
+                assert (_path_in_box(ray, lo, hi) >= 0) == want
+                if want:
+                    assert abs(e - 2.0) <= 0.5 * np.linalg.norm(hi - lo) + 1e-6
+
+
 def test_displacement_vanishes_towards_corners_and_edges(c1):
     pid = int(np.where(c1.types == 1)[0][0])
     cp = c1.cp[pid].astype(np.float64)

@@ -74,3 +74,53 @@ def test_tangent_excuse_is_limited_to_grazing_rays(c1, c1_oracle):
         got = [kk for kk, v in rep["excused"].items() if v]
         assert got == [kind], (i, rep["excused"])
     assert checked == 3
+
+
+def test_graze_excuse_covers_the_box_alg3_records_a_leaf_by(c1):
+    """A hit on a leaf whose Alg. 3 box (the parent's grid half with the parent's
+    displacement, larger than the leaf's own bound for a Gregory patch) the ray only
+    clips by rounding is a graze; one that misses that box by more is hard."""
+    from oracle.parity import _path_in_box
+    L = 4  # coarse leaves, where the two boxes differ by several times the slack
+    osc = O.Scene(c1.cp, c1.types, L)
+    n = 2 ** L
+    uc, vc = (n // 3 + 0.5) / n, (n // 2 + 0.5) / n
+    t_hit = 0.01
+    checked = 0
+    for pid in np.where(c1.types == 1)[0][:20]:
+        lo, hi = osc.leaf_box_alg3(pid, uc, vc)
+        olo, ohi = osc.leaf_box(pid, uc, vc)
+        slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-6 * (t_hit + 1.0)
+        # the box corner (axes a, b; sides sa, sb) where the Alg. 3 box reaches
+        # furthest beyond the leaf's own bound
+        excess = lambda ax, sd: (hi - ohi)[ax] if sd > 0 else (olo - lo)[ax]
+        score, a, b, sa, sb = max((min(excess(a, sa), excess(b, sb)), a, b, sa, sb)
+                                  for a in range(3) for b in range(a + 1, 3) for sa in (1, -1) for sb in (1, -1))
+        if score < 2 * slack:
+            continue
+        corner = np.where([sa > 0, sb > 0], [hi[a], hi[b]], [lo[a], lo[b]])
+        kinds = []
+        for miss in (0.25 * slack, 4.0 * slack):
+            # in the plane of axes a and b, across the corner's diagonal at distance
+            # miss / 2 from the corner: the path in the box is -miss
+            delta = miss / (2.0 * np.sqrt(2.0))
+            p = 0.5 * (lo + hi)
+            p[a], p[b] = corner[0] + sa * delta, corner[1] + sb * delta
+            d = np.zeros(3)
+            d[a], d[b] = sa / np.sqrt(2.0), -sb / np.sqrt(2.0)
+            ray = np.array([*(p - t_hit * d), 0.0, *d, np.inf])
+            assert abs(_path_in_box(ray, lo, hi) + miss) <= 1e-3 * miss
+            assert _path_in_box(ray, olo, ohi) < -slack  # the leaf's own bound alone excuses nothing
+            r32 = ray.astype(np.float32)[None]
+            o = osc.intersect(r32)
+            g = _as_gpu(o)
+            g[0, 0] = t_hit
+            g[0, 1] = np.array([pid], np.uint32).view(np.float32)[0]
+            g[0, 2], g[0, 3] = uc, vc
+            rep = gate(g, o, r32, osc, c1.diameter, L)
+            kinds.append([k for k, v in rep["excused"].items() if v])
+        if ["seam"] in kinds or [] in kinds:
+            continue  # the oracle hit another patch next to this one, or this leaf
+        assert kinds == [["graze"], ["hard"]], (pid, kinds)
+        checked += 1
+    assert checked >= 3
