@@ -226,3 +226,40 @@ def test_graph_captured_refit_intersect_bounce_loop(anim, scene):
         r = eager_rays[f]
         assert_gate(gate(eager[f], osc.intersect(r), r, osc, anim.diameter, anim.leaf_depth,
                          label=f"bounce-frame{f}"))
+
+
+def test_combined_pipeline_with_learned_order(anim, scene):
+    """The combined workload in small: every frame refit, one batched launch of the
+    primary rays of all frames, then two bounce levels, each generated per frame from
+    the previous level's hits and intersected in one batched launch, with the learned
+    child order on (an untrained network: the order never decides a hit).  Every
+    (frame, level) passes the oracle gate on that frame's geometry."""
+    from paper_1811_03510_amd import ccs
+    F, levels = len(anim.frames), 3
+    rng = np.random.default_rng(31)
+    theta = torch.from_numpy((rng.normal(size=ccs.POLICY_PARAMS) * 0.5).astype(np.float32)).cuda()
+    cps = [torch.from_numpy(cp).cuda() for cp in anim.frames]
+    rays = [[torch.from_numpy(r).cuda() for r in anim.rays]]
+    hits = []
+    scene.set_policy(theta)
+    try:
+        for f in range(F):
+            scene.refit_frame(f, cps[f])
+        for b in range(levels):
+            if b > 0:
+                nxt = []
+                for f in range(F):
+                    w = torch.from_numpy(rng.uniform(size=(rays[b - 1][f].shape[0], 2)).astype(np.float32)).cuda()
+                    nxt.append(scene.bounce(rays[b - 1][f], hits[b - 1][f], w, frame=f))
+                rays.append(nxt)
+            hits.append(list(scene.intersect_batched([(f, rays[b][f], None) for f in range(F)])))
+        torch.cuda.synchronize()
+    finally:
+        scene.set_policy(None)
+    for b in range(levels):
+        for f in (0, F - 1):
+            r, h = rays[b][f].cpu().numpy(), hits[b][f].cpu().numpy()
+            osc = O.Scene(anim.frames[f], anim.types, anim.leaf_depth, local_frames=scene.local_frames)
+            _say(f"combined: level {b}, frame {f}: {len(r)} rays")
+            assert_gate(gate(h, osc.intersect(r), r, osc, anim.diameter, anim.leaf_depth,
+                             label=f"combined-level{b}-frame{f}"))
