@@ -233,21 +233,45 @@ def test_refit_matches_oracle_on_moved_scene(ccs, c1, frames):
 
 
 def test_instanced_1m_full_size_sampled(ccs, frames):
-    """1,000,000 patches, 1920x1080 primary + secondary rays in the launch the
-    benchmark times; the oracle checks a seeded sample of each class."""
+    """1,000,000 patches, 1920x1080 primary + secondary rays, one launch per class and
+    both classes in one launch as the benchmark times them, closest-first and learned
+    order; the oracle checks a seeded sample of each class."""
     _say("generating the 1M-patch scene")
     w = S.config2()
     gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
                     local_frames=frames)
     osc = O.Scene(w.cp, w.types, w.leaf_depth, local_frames=frames)
-    for cls, rays in (("primary", w.primary), ("diffuse", w.diffuse)):
+    classes = (("primary", w.primary), ("diffuse", w.diffuse))
+    single = {}
+    for cls, rays in classes:
         _say(f"1M {cls}: {len(rays)} rays on the GPU")
-        g = run(gsc, rays)
+        g = single[cls] = run(gsc, rays)
         sel = S.sample_indices(len(rays), 4096, seed=77 if cls == "primary" else 78)
         o = osc.intersect(rays[sel])
         rep = gate(g[sel], o, rays[sel], osc, w.diameter, w.leaf_depth, label=f"1M-{cls}-sample")
         assert_gate(rep, min_match=0.999)
         assert rep["oracle_hits"] > 500
+    # the benchmark's launch: both classes in one batched launch, bitwise the same hits;
+    # then the same launch with the learned child order (an untrained network) on the
+    # same samples against the oracle
+    dev = [torch.from_numpy(r).cuda() for _, r in classes]
+    both = gsc.intersect_batched([(0, r, None) for r in dev])
+    torch.cuda.synchronize()
+    for (cls, _), h in zip(classes, both):
+        assert np.array_equal(h.cpu().numpy().view(np.uint32), single[cls].view(np.uint32)), cls
+    rng = np.random.default_rng(23)
+    gsc.set_policy(torch.from_numpy((rng.normal(size=ccs.POLICY_PARAMS) * 0.5).astype(np.float32)).cuda())
+    try:
+        _say("1M: learned order, both classes in one launch")
+        learned = gsc.intersect_batched([(0, r, None) for r in dev])
+        torch.cuda.synchronize()
+    finally:
+        gsc.set_policy(None)
+    for (cls, rays), h in zip(classes, learned):
+        sel = S.sample_indices(len(rays), 4096, seed=77 if cls == "primary" else 78)
+        rep = gate(h.cpu().numpy()[sel], osc.intersect(rays[sel]), rays[sel], osc, w.diameter, w.leaf_depth,
+                   label=f"1M-{cls}-learned-sample")
+        assert_gate(rep, min_match=0.999)
 
 
 def test_instanced_1m_refit_to_an_animation_frame(ccs, frames):
