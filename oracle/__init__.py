@@ -24,9 +24,12 @@ COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        # ORACLE_LIB names another build of oracle.cpp (the planted-mistake builds of
+        # tests/test_oracle_mutants.py); by default the one oracle/build.py makes
+        path = os.environ.get("ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         d, u32, i32, vp = C.c_double, C.c_uint32, C.c_int, C.c_void_p
         P = C.POINTER
         L.orc_patch_eval.argtypes = [P(d), i32, d, d, P(d), P(d), P(d)]

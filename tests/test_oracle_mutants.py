@@ -1,0 +1,68 @@
+"""The oracle's pins are sharp: each plausible mistake below, planted in a copy of
+oracle.cpp (CPU only), makes the pin suite fail.  A mistake no pin catches would be
+"parity unpinned"; the list covers each step of the method the oracle computes."""
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_golden.py", "tests/test_oracle_local.py",
+        "tests/test_oracle_whole.py"]
+
+# (name, the passage whose reading the mistake breaks, text in oracle.cpp, planted text)
+MUTANTS = [
+    ("gregory-weight-on-pv", "Sec. 2.2 blend, Alg. 2 weighting (reading R1)",
+     "double lam = du / den;", "double lam = dv / den;"),
+    ("weight-bounds-paired-wrongly", "Sec. 2.2 weight bounds, Alg. 2",
+     "double lam_lo = dul / (dul + dvh), lam_hi = duh / (duh + dvl);",
+     "double lam_lo = dul / (dul + dvl), lam_hi = duh / (duh + dvh);"),
+    ("displacement-dropped", "Sec. 3.2, Alg. 2: d(D)",
+     "d = d + (wbar(i, u0, u1) * wbar(j, v0, v1)) * vabs(A - B);", "d = d + 0.0 * vabs(A - B);"),
+    ("bernstein-peaks-swapped", "Alg. 2: w-bar peaks at 1/3 and 2/3 (reading R3)",
+     "double peak = k == 1 ? 1.0 / 3.0 : 2.0 / 3.0;", "double peak = k == 1 ? 2.0 / 3.0 : 1.0 / 3.0;"),
+    ("crop-v-with-u-range", "Alg. 1 / Sec. 2.1 crop to [u0,u1] x [v0,v1]",
+     "crop1(in, v0, v1, out);", "crop1(in, u0, u1, out);"),
+    ("de-casteljau-wrong-operand", "Sec. 3.1 de Casteljau split",
+     "V3 abc = s * ab + t * bc;", "V3 abc = s * ab + t * cd;"),
+    ("slab-open-interval", "closed slab test (reading R10)",
+     "if (!(near <= far)) return false;", "if (!(near < far)) return false;"),
+    ("leaf-uv-at-corner", "reported (u, v) is the leaf centre (reading R9)",
+     "best.u = (lpu + csu / 2) * kUnit;", "best.u = lpu * kUnit;"),
+    ("farther-child-first", "Sec. 3.3 closest child first",
+     "bool first_r = hr && (!hl || tr < tl);", "bool first_r = hr && (!hl || tr > tl);"),
+    ("frame-not-orthogonal", "Sec. 3.4 patch-local frame (reading R23)",
+     "V3 w = ev - dot(ev, r0) * r0;", "V3 w = ev;"),
+]
+
+
+def _run(tmp, name, old, new):
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"{name}: the planted site is no longer in oracle.cpp"
+    d = os.path.join(tmp, name)
+    os.makedirs(d, exist_ok=True)
+    src, lib = os.path.join(d, "oracle.cpp"), os.path.join(d, "liboracle.so")
+    with open(src, "w") as f:
+        f.write(text.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off", "-o", lib,
+                    src], check=True, capture_output=True)
+    env = dict(os.environ, ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        *PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return name, r.returncode, failed[:1]
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        res = list(ex.map(lambda m: _run(str(tmp_path), m[0], m[2], m[3]), MUTANTS))
+    for name, rc, failed in res:
+        print(f"{name}: exit {rc} {failed}", flush=True)
+    survivors = [name for name, rc, _ in res if rc == 0]
+    assert not survivors, f"planted mistakes that no pin catches: {survivors}"
