@@ -11,8 +11,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
-PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_golden.py", "tests/test_oracle_local.py",
-        "tests/test_oracle_whole.py"]
+# the pins that stand on the paper and the mathematics (closed forms, invariants, brute
+# force, the exact definitions); the stored-fixture regression test is left out
+PINS = ["tests/test_oracle_pins.py", "tests/test_oracle_local.py", "tests/test_oracle_whole.py"]
 
 # (name, the passage whose reading the mistake breaks, text in oracle.cpp, planted text)
 MUTANTS = [
@@ -37,6 +38,10 @@ MUTANTS = [
      "bool first_r = hr && (!hl || tr < tl);", "bool first_r = hr && (!hl || tr > tl);"),
     ("frame-not-orthogonal", "Sec. 3.4 patch-local frame (reading R23)",
      "V3 w = ev - dot(ev, r0) * r0;", "V3 w = ev;"),
+    ("frame-boxes-not-grown", "Sec. 3.4 growing boxes to close gaps (reading R23)",
+     "Q.pad = std::ldexp(std::max(ext.x, std::max(ext.y, ext.z)), -19);", "Q.pad = 0.0 * ext.x;"),
+    ("one-split-short", "fixed leaf depth L per axis (reading R7)",
+     "const int leaf_depth = 2 * L;", "const int leaf_depth = 2 * L - 1;"),
 ]
 
 
