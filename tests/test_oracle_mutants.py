@@ -45,6 +45,48 @@ MUTANTS = [
 ]
 
 
+# Mistakes in the FP64 references of the learned child ordering (oracle/mlp.py: the
+# network, its loss and training step; oracle/policy.py: its inputs and labels),
+# checked against tests/test_oracle_mlp.py in a copy of the test tree.
+PY_MUTANTS = [
+    ("relu-gate-dropped", "mlp.py", "backpropagation through the second ReLU",
+     'd2 = (d3 @ p["W3"]) * (c["a2"] > 0)', 'd2 = (d3 @ p["W3"])'),
+    ("bias-gradient-averaged", "mlp.py", "gradient of the first bias",
+     'g["W1"], g["b1"] = d1.T @ c["x"], d1.sum(axis=0)', 'g["W1"], g["b1"] = d1.T @ c["x"], d1.mean(axis=0)'),
+    ("bf16-rounds-ties-up", "mlp.py", "bfloat16 rounding to nearest even (reading R22)",
+     "b = (b + 0x7FFF + ((b >> 16) & 1)) >> 16", "b = (b + 0x8000) >> 16"),
+    ("adam-without-bias-correction", "mlp.py", "Adam's bias-corrected moments",
+     "mh = m / (1.0 - beta1 ** t)", "mh = m"),
+    ("order-projection-swapped", "mlp.py", "the top grandchild's u-half first (reading R18)",
+     "return top >> 1, top & 1", "return top & 1, top >> 1"),
+    ("onb-left-handed", "policy.py", "the ray frame of Duff et al. 2017 (reading R17)",
+     "e2 = np.array([b, sign + n[1] * n[1] * a, -n[1]])", "e2 = -np.array([b, sign + n[1] * n[1] * a, -n[1]])"),
+    ("entry-point-at-exit", "policy.py", "corners relative to the node box's entry point (reading R17)",
+     "p = o + min(na, nb) * d", "p = o + max(na, nb) * d"),
+    ("label-bits-swapped", "policy.py", "labels name the grandchild holding the leaf (reading R19)",
+     "labels[k] = 2 * ((iu >> (L - 1 - k)) & 1) + ((iv >> (L - 1 - k)) & 1)",
+     "labels[k] = 2 * ((iv >> (L - 1 - k)) & 1) + ((iu >> (L - 1 - k)) & 1)"),
+]
+
+
+def _run_py(tmp, name, fname, old, new):
+    d = os.path.join(tmp, name)
+    for sub in ("oracle", "tests", "paper_1811_03510_amd"):
+        shutil.copytree(os.path.join(ROOT, sub), os.path.join(d, sub),
+                        ignore=shutil.ignore_patterns("__pycache__", "_build", "*.so", "csrc", "*.o"))
+    shutil.copy(os.path.join(ROOT, "oracle", "liboracle.so"), os.path.join(d, "oracle", "liboracle.so"))
+    path = os.path.join(d, "oracle", fname)
+    text = open(path).read()
+    assert text.count(old) == 1, f"{name}: the planted site is no longer in oracle/{fname}"
+    with open(path, "w") as f:
+        f.write(text.replace(old, new))
+    env = {k: v for k, v in os.environ.items() if k != "ORACLE_LIB"}
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                        "tests/test_oracle_mlp.py"], cwd=d, env=env, capture_output=True, text=True, timeout=600)
+    failed = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED")]
+    return name, r.returncode, failed[:1]
+
+
 def _run(tmp, name, old, new):
     text = open(SRC).read()
     assert text.count(old) == 1, f"{name}: the planted site is no longer in oracle.cpp"
@@ -65,8 +107,27 @@ def _run(tmp, name, old, new):
 @pytest.mark.slow
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
 def test_every_planted_mistake_fails_a_pin(tmp_path):
+    # control: the same harness on an unaltered copy passes, so a failure means the mistake
+    site = MUTANTS[0][2]
     with ThreadPoolExecutor(max_workers=4) as ex:
-        res = list(ex.map(lambda m: _run(str(tmp_path), m[0], m[2], m[3]), MUTANTS))
+        res = list(ex.map(lambda m: _run(str(tmp_path), m[0], m[2], m[3]), [("control", "", site, site)] + MUTANTS))
+    assert res[0][1] == 0, f"the unaltered copy fails the pins: {res[0]}"
+    res = res[1:]
+    for name, rc, failed in res:
+        print(f"{name}: exit {rc} {failed}", flush=True)
+    survivors = [name for name, rc, _ in res if rc == 0]
+    assert not survivors, f"planted mistakes that no pin catches: {survivors}"
+
+
+@pytest.mark.slow
+def test_every_planted_mistake_in_the_learned_order_references_fails_a_pin(tmp_path):
+    assert os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so"))
+    site = PY_MUTANTS[0][3]
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        res = list(ex.map(lambda m: _run_py(str(tmp_path), m[0], m[1], m[3], m[4]),
+                          [("control", "mlp.py", "", site, site)] + PY_MUTANTS))
+    assert res[0][1] == 0, f"the unaltered copy fails the pins: {res[0]}"
+    res = res[1:]
     for name, rc, failed in res:
         print(f"{name}: exit {rc} {failed}", flush=True)
     survivors = [name for name, rc, _ in res if rc == 0]
