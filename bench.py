@@ -428,8 +428,9 @@ def main():
         osec = time.time() - t0
         cpu = {"value": round(2 * k / osec / 1e6, 4), "unit": "MRays/s", "cores": threads, "kind": "oracle",
                "per_core": round(2 * k / osec / 1e6 / threads, 5), "cpu_model": cpu_model(),
-               "sample": f"{k} primary + {k} secondary rays (seeded subset of the same {n_p}+{n_d} rays), "
-                         f"{osec:.1f} s; oracle BVH build {obuild:.1f} s excluded"}
+               "sample": (f"all {n_p} primary + {n_d} secondary rays of the workload" if k >= max(n_p, n_d) else
+                          f"{k} primary + {k} secondary rays (seeded subset of the same {n_p}+{n_d} rays)")
+                         + f", {osec:.1f} s; oracle BVH build {obuild:.1f} s excluded"}
         rp = gate(hits_p[sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="primary")
         rd = gate(hits_d[sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="diffuse")
         parity = {c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
