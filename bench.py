@@ -47,6 +47,8 @@ OPS_PER_UNIT = {
     "leaf": 30,        # leaf record: compare, (u, v) from the path code
     "crop": 502,       # Bezier grid recompute after backtracking (crop to the domain)
 }
+# Smallest seeded sample, per ray class, on which a variant's hits are gated against the oracle.
+MIN_GATE_RAYS = 131072
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # CUs x SIMDs x lanes x clock: 39.32 T lane-op/s
 COUNTERS = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
 
@@ -78,9 +80,9 @@ def algorithmic_ops(cnt: np.ndarray) -> float:
     return float(ops)
 
 
-def traffic_from_profiles(kernel_ms_avg: float):
-    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE), scaled
-    by the copy-kernel calibration, when recorded for the current kernel sources."""
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE),
+    scaled by the copy-kernel calibration, when recorded for the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "intersect_traffic.json")
     if not os.path.exists(path):
         return None
@@ -88,7 +90,7 @@ def traffic_from_profiles(kernel_ms_avg: float):
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("source_hash") != source_hash():
+    if rec.get("source_hash") != source_hash() or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
 
@@ -284,6 +286,7 @@ def main():
                 and np.array_equal(hits_d.view(np.uint32), hd.cpu().numpy().view(np.uint32)))
         log(f"batched: {ms:.3f} ms/step -> {variants['batched']['mrays_per_s']:.1f} MRays/s "
             f"(launch {variants['batched']['launch']})")
+    world_hits = None
     if args.only == "" and not args.world_frames:
         # the same launch with subdivision in world coordinates, for the Sec. 3.4 comparison
         wsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth)
@@ -299,6 +302,7 @@ def main():
                 evs[1].record(stream)
 
         laps, ms = timed(world_step, 2)
+        world_hits = (wh[0].cpu().numpy(), wh[1].cpu().numpy())
         variants["batched_world_frames"] = {
             "ms_per_step": ms, "mrays_per_s": (n_p + n_d) / (ms * 1e-3) / 1e6, "launches_per_step": 1,
             "kernel_ms": float(np.mean(laps)), "note": "closest-first, both classes in one launch, world frame"}
@@ -327,14 +331,28 @@ def main():
 
         laps, ms = timed(bounce_step, 2)
         nb = brays.shape[0]
+        bh_only = torch.empty_like(bh)
+
+        def bounce_only_step(evs=None):
+            if evs:
+                evs[0].record(stream)
+            scene.intersect(brays, bh_only)
+            if evs:
+                evs[1].record(stream)
+
+        laps_b, _ = timed(bounce_only_step, 2)
         variants["batched_bounce"] = {
             "ms_per_step": ms, "mrays_per_s": (n_p + nb) / (ms * 1e-3) / 1e6, "launches_per_step": 1,
             "kernel_ms": float(np.mean(laps)), "rays": {"primary": n_p, "bounce": nb},
             "bounce_hit_fraction": float((bh[:, 0] < float("inf")).float().mean().item()) if nb else 0.0,
-            "note": "closest-first, primary rays plus one GPU-generated bounce per primary hit, one launch"}
-        bounce = (brays.cpu().numpy(), bh.cpu().numpy())
+            "per_class": {"bounce": cls(nb, laps_b[:, 0], bh_only.cpu().numpy())},
+            "note": "closest-first; the configuration's own secondary rays: one cosine bounce per primary hit "
+                    "(ccs_bounce on the GPU's hits), primary and bounce rays in one launch; per_class.bounce "
+                    "times the bounce rays alone in a launch of their own"}
+        bounce = (brays.cpu().numpy(), bh.cpu().numpy(), hp2.cpu().numpy())
         log(f"batched with real bounces ({nb} bounce rays): {ms:.3f} ms/step -> "
-            f"{variants['batched_bounce']['mrays_per_s']:.1f} MRays/s")
+            f"{variants['batched_bounce']['mrays_per_s']:.1f} MRays/s; bounce rays alone "
+            f"{variants['batched_bounce']['per_class']['bounce']['mrays_per_s']:.1f} MRays/s")
     learned_hits = None
     if args.only in ("", "learned"):
         policy, pstats = train_policy(args, torch, ccs, scenes)
@@ -371,41 +389,15 @@ def main():
         scene.set_policy(None)
         variants["learned_batched"] = v
         log(f"learned batched: {ms:.3f} ms/step -> {v['mrays_per_s']:.1f} MRays/s; {pstats}")
-    head = "batched" if "batched" in variants else ("plain" if "plain" in variants else "learned_batched")
-    if "learned_batched" in variants and head != "learned_batched" and \
-            variants["learned_batched"]["mrays_per_s"] > variants[head]["mrays_per_s"]:
-        head = "learned_batched"  # kept only if it also passes the oracle gate below
-    ms_step = variants[head]["ms_per_step"]
-    value = variants[head]["mrays_per_s"]
-
-    roofline = None
-    work = None
-    if not args.no_counters:
-        if head == "learned_batched":
-            scene.set_policy(policy)
-        _, cp_ = scene.intersect_counted(prim)
-        _, cd_ = scene.intersect_counted(diff)
-        torch.cuda.synchronize()
-        scene.set_policy(None)
-        cp_, cd_ = cp_.cpu().numpy(), cd_.cpu().numpy()
-        ops_p, ops_d = algorithmic_ops(cp_), algorithmic_ops(cd_)
-        per_launch = variants[head]["launches_per_step"]
-        launch_ms = variants[head]["kernel_ms"]
-        ops_launch = (ops_p + ops_d) / per_launch
-        achieved = ops_launch / (launch_ms * 1e-3) / 1e12
-        bytes_launch = traffic_from_profiles(launch_ms)
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
-                    "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
-                    "traffic": bytes_launch if head != "learned_batched" else None,
-                    "kernel": "k_trace<false, true>" if head == "learned_batched" else "k_trace<false, false>",
-                    "kernel_avg_ms": round(launch_ms, 4),
-                    "ops_per_launch": ops_launch,
-                    "ops_per_ray": {"primary": ops_p / n_p, "diffuse": ops_d / n_d}}
-        work = {c: {"primary": float(cp_[:, k].mean()), "diffuse": float(cd_[:, k].mean())}
-                for k, c in enumerate(COUNTERS)}
-
+    # ------------------------------------------------------------ oracle gate
+    # Every timed variant's hits are gated against the FP64 oracle on seeded samples
+    # (closest-first: the batched launch's hits, bit-identical to the plain launches';
+    # world frames: against the world-frame oracle; bounce: the configuration's own
+    # secondary rays; learned order).  A variant that fails reports no MRays/s, and
+    # any failure withholds the headline value and ends the run with status 1.
     cpu = None
     parity = None
+    gates = {}
     if not args.no_cpu_baseline:
         import oracle
         from oracle.parity import gate
@@ -419,7 +411,7 @@ def main():
         osc.intersect(w.primary[calib], nthreads=threads)
         osc.intersect(w.diffuse[calib], nthreads=threads)
         per_ray = (time.time() - t0) / (2 * len(calib))
-        k = int(min(max(2048, args.cpu_seconds / max(per_ray, 1e-9) / 2), n_p, n_d))
+        k = int(min(max(MIN_GATE_RAYS, args.cpu_seconds / max(per_ray, 1e-9) / 2), n_p, n_d))
         sel_p = scenes.sample_indices(n_p, k, seed=92)
         sel_d = scenes.sample_indices(n_d, k, seed=93)
         t0 = time.time()
@@ -431,40 +423,103 @@ def main():
                "sample": (f"all {n_p} primary + {n_d} secondary rays of the workload" if k >= max(n_p, n_d) else
                           f"{k} primary + {k} secondary rays (seeded subset of the same {n_p}+{n_d} rays)")
                          + f", {osec:.1f} s; oracle BVH build {obuild:.1f} s excluded"}
-        rp = gate(hits_p[sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="primary")
-        rd = gate(hits_d[sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="diffuse")
-        parity = {c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
-                      "excused": r["excused"], "ok": r["ok"]} for c, r in (("primary", rp), ("diffuse", rd))}
+
+        def summary(r):
+            return {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
+                    "excused": r["excused"], "ok": r["ok"], "hard_examples": r["hard"][:3]}
+
+        if "batched" in variants or "plain" in variants:
+            # the closest-first hits (the batched launch's when it ran: bit-identical to the
+            # plain launches', which bench reports as bitwise_equal_to_plain)
+            cf_hits = (hits_p, hits_d)
+            rp = gate(cf_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="primary")
+            rd = gate(cf_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="diffuse")
+            parity = {"primary": summary(rp), "diffuse": summary(rd)}
+            ok_cf = rp["ok"] and rd["ok"]
+            if "batched" in variants:
+                gates["batched"] = ok_cf
+            if "plain" in variants:  # gated directly, or through its bitwise equality with the batched hits
+                gates["plain"] = ok_cf and variants.get("batched", {}).get("bitwise_equal_to_plain", True)
         if bounce is not None:
-            sel_b = scenes.sample_indices(len(bounce[0]), min(len(bounce[0]), 65536), seed=94)
+            sel_b = scenes.sample_indices(len(bounce[0]), min(len(bounce[0]), MIN_GATE_RAYS), seed=94)
             ob = osc.intersect(bounce[0][sel_b], nthreads=threads)
             rb = gate(bounce[1][sel_b], ob, bounce[0][sel_b], osc, w.diameter, w.leaf_depth, label="bounce")
-            variants["batched_bounce"]["parity_sample"] = {"rays": rb["n"], "same_hit_and_patch": rb["id_rate"],
-                                                           "excused": rb["excused"], "ok": rb["ok"]}
+            stride = max(1, len(sel_p) // MIN_GATE_RAYS)  # a spread subset of the primary sample
+            sel_bp = sel_p[::stride]
+            rbp = gate(bounce[2][sel_bp], {kk: vv[::stride] for kk, vv in op.items()}, w.primary[sel_bp], osc,
+                       w.diameter, w.leaf_depth, label="bounce-launch primary")
+            variants["batched_bounce"]["parity_sample"] = {"bounce": summary(rb), "primary": summary(rbp)}
+            gates["batched_bounce"] = rb["ok"] and rbp["ok"]
         if learned_hits is not None:
             lp_ = gate(learned_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="l-primary")
             ld_ = gate(learned_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="l-diffuse")
-            variants["learned_batched"]["parity_sample"] = {
-                c: {"rays": r["n"], "same_hit_and_patch": r["id_rate"], "strict": r["match_rate"],
-                    "excused": r["excused"], "ok": r["ok"]} for c, r in (("primary", lp_), ("diffuse", ld_))}
-            if head == "learned_batched" and not (lp_["ok"] and ld_["ok"]):
-                head = "batched" if "batched" in variants else "plain"  # a failing variant reports nothing
-                ms_step, value = variants[head]["ms_per_step"], variants[head]["mrays_per_s"]
-        log(f"cpu baseline: {cpu['value']} MRays/s on {threads} threads; parity {parity}")
-        if not (rp["ok"] and rd["ok"]):
-            # the closest-first hits are the batched and plain variants' (bit-identical):
-            # no timed variant is oracle-exact then, and the line says so
-            print(f"bench: PARITY FAILED on the oracle sample: primary {rp['excused']}, diffuse {rd['excused']}, "
-                  f"hard examples {rp['hard'] + rd['hard']}", file=sys.stderr, flush=True)
+            variants["learned_batched"]["parity_sample"] = {"primary": summary(lp_), "diffuse": summary(ld_)}
+            gates["learned_batched"] = lp_["ok"] and ld_["ok"]
+        del osc
+        if world_hits is not None:
+            osw = oracle.Scene(w.cp, w.types, w.leaf_depth, local_frames=False)
+            sw_p = scenes.sample_indices(n_p, MIN_GATE_RAYS, seed=95)
+            sw_d = scenes.sample_indices(n_d, MIN_GATE_RAYS, seed=96)
+            ow_p = osw.intersect(w.primary[sw_p], nthreads=threads)
+            ow_d = osw.intersect(w.diffuse[sw_d], nthreads=threads)
+            rwp = gate(world_hits[0][sw_p], ow_p, w.primary[sw_p], osw, w.diameter, w.leaf_depth,
+                       label="world primary")
+            rwd = gate(world_hits[1][sw_d], ow_d, w.diffuse[sw_d], osw, w.diameter, w.leaf_depth,
+                       label="world diffuse")
+            variants["batched_world_frames"]["parity_sample"] = {"primary": summary(rwp), "diffuse": summary(rwd)}
+            gates["batched_world_frames"] = rwp["ok"] and rwd["ok"]
+            del osw
+        log(f"cpu baseline: {cpu['value']} MRays/s on {threads} threads; gates {gates}; parity {parity}")
+        for v, ok in gates.items():
+            variants[v]["gate_ok"] = ok
+            if not ok:
+                variants[v]["mrays_per_s"] = None
+                print(f"bench: PARITY FAILED for variant {v}", file=sys.stderr, flush=True)
+
+    # headline: the faster of closest-first and learned order among the variants that
+    # passed the gate; without the oracle only closest-first is reported
+    cands = [v for v in ("batched", "plain") if v in variants][:1]
+    if "learned_batched" in variants and gates.get("learned_batched"):
+        cands.append("learned_batched")
+    cands = [v for v in cands if variants[v]["mrays_per_s"] is not None]
+    head = max(cands, key=lambda v: variants[v]["mrays_per_s"]) if cands else None
+    failed = [v for v, ok in gates.items() if not ok]
+    value = None if (failed or head is None) else variants[head]["mrays_per_s"]
+    ms_step = variants[head]["ms_per_step"] if head else None
+
+    roofline = None
+    work = None
+    if not args.no_counters and head is not None:
+        if head == "learned_batched":
+            scene.set_policy(policy)
+        _, cp_ = scene.intersect_counted(prim)
+        _, cd_ = scene.intersect_counted(diff)
+        torch.cuda.synchronize()
+        scene.set_policy(None)
+        cp_, cd_ = cp_.cpu().numpy(), cd_.cpu().numpy()
+        ops_p, ops_d = algorithmic_ops(cp_), algorithmic_ops(cd_)
+        per_launch = variants[head]["launches_per_step"]
+        launch_ms = variants[head]["kernel_ms"]
+        ops_launch = (ops_p + ops_d) / per_launch
+        achieved = ops_launch / (launch_ms * 1e-3) / 1e12
+        kname = "k_trace<false, true>" if head == "learned_batched" else "k_trace<false, false>"
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
+                    "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4),
+                    "traffic": traffic_from_profiles(kname),
+                    "kernel": kname, "kernel_avg_ms": round(launch_ms, 4),
+                    "ops_per_launch": ops_launch,
+                    "ops_per_ray": {"primary": ops_p / n_p, "diffuse": ops_d / n_d}}
+        work = {c: {"primary": float(cp_[:, k].mean()), "diffuse": float(cd_[:, k].mean())}
+                for k, c in enumerate(COUNTERS)}
 
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": None if value is None else round(value, 3),
         "unit": "MRays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": None if ms_step is None else round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -472,24 +527,30 @@ def main():
         "data": "synthetic (seeded)",
         "config": {"workload": (f"{w.name}: {w.cp.shape[0]} patches "
                                 f"({int(w.types.sum())} Gregory), {n_p} primary + {n_d} secondary rays per step"),
-                   "variant": {"plain": "closest-first order, one launch per ray class",
+                   "variant": {None: "none passed the oracle gate",
+                               "plain": "closest-first order, one launch per ray class",
                                "batched": "closest-first order, both ray classes in one autotuned launch",
                                "learned_batched": "learned child order, both ray classes in one autotuned launch"
                                }[head],
-                   "launch": variants[head]["launch"],
+                   "launch": variants[head]["launch"] if head else None,
                    "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
-                   "leaf_depth": w.leaf_depth},
+                   "leaf_depth": w.leaf_depth,
+                   "secondary_rays": "stand-in: one cosine-weighted ray per pixel from a seeded surface point; "
+                                     "variants.batched_bounce has the configuration's own bounce per primary hit"},
         "variants": variants,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
-        "parity_ok": None if parity is None else bool(all(c["ok"] for c in parity.values())),
+        "parity_ok": None if not gates else not failed,
+        "gate_failed": failed,
         "work_per_ray": work,
         "scene": {"create_s": round(create_s, 3), "bvh_build_s": round(info["build_seconds"], 3),
                   "bvh_depth": info["bvh_depth"], "device_mib": round(info["device_bytes"] / 2**20, 1)},
         "source_hash": source_hash(),
     }
     print(json.dumps(out), flush=True)
+    if failed:
+        sys.exit(1)
 
 
 def cpu_model() -> str:

@@ -7,14 +7,28 @@ excused only when the paper's error model explains it:
              entered within 1e-5 max(t, 1) of the oracle's best distance (its
              own t within the 1e-4 D tolerance): two leaves or patches are then
              equally correct answers (Sec. 3.3 records the closest box);
-  * seam  -- different patches: the two hit points are within 1e-4 D of each
-             other, or a reported (u, v) lies within 2^-L of its patch boundary
-             (shared edges); a different leaf of the same patch is never a seam;
-  * graze -- the ray only clips the leaf box the side that hit reported (the box
-             Alg. 3 tests, the leaf's half of its parent's grid with the parent's
-             displacement, or the leaf's own bound): its path inside that box is
-             shorter than 1e-3 of the box diagonal (plus 1e-6 (t + 1) of
-             rounding): silhouettes, box edges and corners;
+  * seam  -- different patches meeting at a shared edge: the two hit points are
+             within 1e-4 D of each other AND at least one reported (u, v) lies
+             within 2^-L of its patch boundary (Sec. 3.4: neighbours share their
+             boundary curves, so a ray through the seam may name either).  A hit
+             near an edge on a patch farther along the ray (a ray slipping through
+             a crack) is hard; a different leaf of the same patch is never a seam;
+  * graze -- the ray passes within 1e-3 of the box diagonal (plus 1e-7 (t + 1)
+             of rounding) of the silhouette of the leaf box one side reported (the
+             box Alg. 3 tests, the leaf's half of its parent's grid with the
+             parent's displacement, or the leaf's own bound), inside or outside it:
+             moving the ray sideways by that much would make it miss or hit the box
+             (silhouettes, box edges and corners).  Only the nearer answer can be
+             excused this way: a grazed oracle leaf when the GPU missed it and
+             reports a farther hit or none, a grazed GPU leaf when the oracle missed
+             it and reports a farther hit or none.  The oracle confirms it: the
+             ray moved sideways out of the oracle's grazed box (or into the GPU's)
+             by the margin and a little more must give the GPU's answer (the same
+             patch within the distance tolerance, or a miss), so that a GPU that
+             skipped a leaf whose neighbour the ray would then meet is not excused.
+             (The margin is measured across the ray because a leaf box is often
+             thin: the path along the ray through a flat box is short wherever the
+             ray crosses it.);
   * tangent -- same patch, |dt| within tolerance, the ray within 1.2 degrees of
              tangent to the surface at the oracle's hit (|cos| < 0.02), and the
              surface at the GPU's (u, v) within the GPU leaf box's diagonal of the
@@ -49,6 +63,58 @@ def _path_in_box(ray, lo, hi):
         t0, t1 = (lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]
         near, far = max(near, min(t0, t1)), min(far, max(t0, t1))
     return (far - near) * np.linalg.norm(d)  # negative when the box is missed
+
+
+def _lateral_margin(ray, lo, hi):
+    """Signed distance, across the ray, from the ray's line to the silhouette of the
+    box [lo, hi], and the unit vector (normal to the ray) pointing from the line to
+    the nearest point of that silhouette.  The box projected along the ray's
+    direction onto the plane through the origin normal to it is a convex polygon;
+    the distance is positive when the line passes inside it (the distance to its
+    boundary), negative outside (minus the distance to it).  The ray is the 8-float
+    record {o, tmin, d, tmax}."""
+    o, d = np.asarray(ray[:3], np.float64), np.asarray(ray[4:7], np.float64)
+    dn = d / np.linalg.norm(d)
+    a = np.array([1.0, 0.0, 0.0]) if abs(dn[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(dn, a)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(dn, e1)
+    corners = np.array([[(hi if (c >> k) & 1 else lo)[k] for k in range(3)] for c in range(8)]) - o
+    pts = sorted(set((float(p @ e1), float(p @ e2)) for p in corners))
+    cross = lambda o_, a_, b_: (a_[0] - o_[0]) * (b_[1] - o_[1]) - (a_[1] - o_[1]) * (b_[0] - o_[0])
+    hull = []
+    for seq in (pts, pts[::-1]):  # monotone chain: lower, then upper hull
+        part = []
+        for p in seq:
+            while len(part) >= 2 and cross(part[-2], part[-1], p) <= 0.0:
+                part.pop()
+            part.append(p)
+        hull += part[:-1]
+    hull = np.array(hull) if hull else np.array(pts[:1])
+
+    def nearest(a_, b_):  # point of segment a_ b_ nearest to the origin
+        ab = b_ - a_
+        den = ab @ ab
+        s_ = 0.0 if den == 0.0 else min(max(-(a_ @ ab) / den, 0.0), 1.0)
+        return a_ + s_ * ab
+
+    m = len(hull)
+    q = min((nearest(hull[k], hull[(k + 1) % m]) for k in range(m)), key=lambda x: float(x @ x))
+    dist = float(np.linalg.norm(q))
+    w = (q[0] * e1 + q[1] * e2) / dist if dist > 0.0 else e1
+    # a box projecting to a segment or a point has no inside
+    inside = m >= 3 and all(cross(hull[k], hull[(k + 1) % m], (0.0, 0.0)) >= 0.0 for k in range(m))
+    return (dist if inside else -dist), w
+
+
+def _moved_ray(ray, shift, t_ref, reach):
+    """The ray moved sideways by `shift` (world), its origin also moved along it to
+    parameter max(tmin, t_ref - reach) so that the fp32 record stays close to the
+    hit; returns (fp32 ray, parameter offset of the new origin)."""
+    o, d = np.asarray(ray[:3], np.float64), np.asarray(ray[4:7], np.float64)
+    s0 = max(float(ray[3]), t_ref - reach)
+    out = np.array([*(o + s0 * d + shift), 0.0, *d, float(ray[7]) - s0])
+    return out.astype(np.float32), s0
 
 
 def _in_frame(osc, pid, ray):
@@ -93,8 +159,8 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
             xg, xo = o64 + gt[k] * d64, o64 + ora["t"][k] * d64
             m = 2.0 ** -leaf_depth
             near_edge = lambda u, v: min(u, v, 1 - u, 1 - v) <= m * (1 + 1e-6)
-            if np.linalg.norm(xg - xo) <= tol_t or near_edge(gpu[k, 2], gpu[k, 3]) or \
-                    near_edge(ora["u"][k], ora["v"][k]):
+            if np.linalg.norm(xg - xo) <= tol_t and (near_edge(gpu[k, 2], gpu[k, 3]) or
+                                                      near_edge(ora["u"][k], ora["v"][k])):
                 kind = "seam"
         if kind == "hard" and g_hit[k] and o_hit[k] and gid[k] == oid[k] and dt_ok[k]:
             pid = int(gid[k])
@@ -111,17 +177,45 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
                 if dist <= np.linalg.norm(hi - lo) + 1e-6 * (abs(gt[k]) + 1.0):
                     kind = "tangent"
         if kind == "hard":
-            # the side that hit: does the ray merely clip its leaf box, the box Alg. 3
-            # tests (the half of the parent's grid grown by the parent's displacement)
-            # or the leaf's own bound?  (Boxes are in the patch's frame, where the ray
-            # is taken too.)
-            for side_hit, pid, u, v, t in ((o_hit[k], oid[k], ora["u"][k], ora["v"][k], ora["t"][k]),
-                                           (g_hit[k], gid[k], gpu[k, 2], gpu[k, 3], gt[k])):
-                if side_hit and kind == "hard":
+            # the nearer side's leaf: does the ray pass within rounding of its box's
+            # silhouette, the box Alg. 3 tests (the half of the parent's grid grown by
+            # the parent's displacement) or the leaf's own bound?  (Boxes are in the
+            # patch's frame, where the ray is taken too.)  The oracle's grazed leaf
+            # excuses a GPU that missed it only if the GPU's answer is not nearer, and
+            # the GPU's grazed leaf a oracle that missed it only if the oracle's
+            # answer is not nearer.
+            tol_ord = 1e-5 * max(abs(ora["t"][k]) if o_hit[k] else abs(gt[k]), 1.0)
+            o_first = o_hit[k] and (not g_hit[k] or gt[k] >= ora["t"][k] - tol_ord)
+            g_first = g_hit[k] and (not o_hit[k] or gt[k] <= ora["t"][k] + tol_ord)
+            for side, side_ok, pid, u, v, t in (("oracle", o_first, oid[k], ora["u"][k], ora["v"][k], ora["t"][k]),
+                                                ("gpu", g_first, gid[k], gpu[k, 2], gpu[k, 3], gt[k])):
+                if side_ok and kind == "hard":
+                    R = osc.patch_frame(int(pid))
                     rf = _in_frame(osc, pid, ray)
                     for lo, hi in (osc.leaf_box_alg3(pid, u, v), osc.leaf_box(pid, u, v)):
-                        slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-6 * (abs(t) + 1.0)
-                        if abs(_path_in_box(rf, lo, hi)) <= slack:
+                        diag = float(np.linalg.norm(hi - lo))
+                        slack = 1e-3 * diag + 1e-7 * (abs(t) + 1.0)
+                        mgn, w = _lateral_margin(rf, lo, hi)
+                        if abs(mgn) > slack:
+                            continue
+                        # confirm with the oracle itself: the ray moved sideways out of the
+                        # oracle's grazed box (into the GPU's grazed box) by the margin and a
+                        # little more must give the GPU's answer
+                        reach = 4.0 * diag / float(np.linalg.norm(ray[4:7].astype(np.float64)))
+                        o2 = ray[:3].astype(np.float64) + max(float(ray[3]), t - reach) * ray[4:7]
+                        extra = slack + 16.0 * 2.0 ** -24 * float(np.abs(o2).max())
+                        if side == "oracle":
+                            step = (mgn + extra) if mgn >= 0.0 else -extra
+                        else:
+                            step = (-mgn + extra) if mgn < 0.0 else -extra
+                        r2, s0 = _moved_ray(ray, R.T @ (step * w), t, reach)
+                        o2r = osc.intersect(r2[None])
+                        t2, id2 = float(o2r["t"][0]) + s0, int(o2r["id"][0])
+                        if not g_hit[k]:
+                            agree = id2 == NO_HIT
+                        else:
+                            agree = id2 == int(gid[k]) and abs(t2 - gt[k]) <= tol_t
+                        if agree:
                             kind = "graze"
                             break
         kinds[kind] += 1

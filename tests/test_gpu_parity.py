@@ -12,6 +12,9 @@ from oracle.parity import assert_gate, gate, ids_of
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+# rays per class the oracle checks at full size (same hit/miss and patch on >= 99.99 %)
+GATE_RAYS = 131072
+
 
 def _say(*a):
     print(*a, flush=True)
@@ -235,7 +238,7 @@ def test_refit_matches_oracle_on_moved_scene(ccs, c1, frames):
 def test_instanced_1m_full_size_sampled(ccs, frames):
     """1,000,000 patches, 1920x1080 primary + secondary rays, one launch per class and
     both classes in one launch as the benchmark times them, closest-first and learned
-    order; the oracle checks a seeded sample of each class."""
+    order; the oracle checks a seeded sample of 131,072 rays of each class."""
     _say("generating the 1M-patch scene")
     w = S.config2()
     gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
@@ -246,10 +249,10 @@ def test_instanced_1m_full_size_sampled(ccs, frames):
     for cls, rays in classes:
         _say(f"1M {cls}: {len(rays)} rays on the GPU")
         g = single[cls] = run(gsc, rays)
-        sel = S.sample_indices(len(rays), 4096, seed=77 if cls == "primary" else 78)
+        sel = S.sample_indices(len(rays), GATE_RAYS, seed=77 if cls == "primary" else 78)
         o = osc.intersect(rays[sel])
         rep = gate(g[sel], o, rays[sel], osc, w.diameter, w.leaf_depth, label=f"1M-{cls}-sample")
-        assert_gate(rep, min_match=0.999)
+        assert_gate(rep)
         assert rep["oracle_hits"] > 500
     # the benchmark's launch: both classes in one batched launch, bitwise the same hits;
     # then the same launch with the learned child order (an untrained network) on the
@@ -268,10 +271,10 @@ def test_instanced_1m_full_size_sampled(ccs, frames):
     finally:
         gsc.set_policy(None)
     for (cls, rays), h in zip(classes, learned):
-        sel = S.sample_indices(len(rays), 4096, seed=77 if cls == "primary" else 78)
+        sel = S.sample_indices(len(rays), GATE_RAYS, seed=77 if cls == "primary" else 78)
         rep = gate(h.cpu().numpy()[sel], osc.intersect(rays[sel]), rays[sel], osc, w.diameter, w.leaf_depth,
                    label=f"1M-{cls}-learned-sample")
-        assert_gate(rep, min_match=0.999)
+        assert_gate(rep)
 
 
 def test_instanced_1m_refit_to_an_animation_frame(ccs, frames):
@@ -283,10 +286,10 @@ def test_instanced_1m_refit_to_an_animation_frame(ccs, frames):
     gsc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
                     local_frames=frames)
     gsc.refit(torch.from_numpy(cp1).cuda())
-    sel = S.sample_indices(len(w.primary), 8192, seed=79)
+    sel = S.sample_indices(len(w.primary), GATE_RAYS, seed=79)
     rays = w.primary[sel]
     g = run(gsc, rays)
     osc = O.Scene(cp1, w.types, w.leaf_depth, local_frames=frames)
     rep = gate(g, osc.intersect(rays), rays, osc, w.diameter, w.leaf_depth, label="1M-refit-frame5")
-    assert_gate(rep, min_match=0.999)
+    assert_gate(rep)
     assert rep["oracle_hits"] > 1000
