@@ -336,6 +336,15 @@ struct Split {
   uint32_t pu, pv, su, sv;
 };
 
+// Hindsight order (measurement only): the patch and leaf corner (units of 2^-23) of
+// a ray's known closest hit.  On that patch, wherever both halves of a split are
+// hit and they are not the leaf pair, the half holding that leaf is visited first
+// instead of the closer one: the ordering a perfect predictor of the final leaf
+// would give, to bound what any learned child order can save.
+struct OrderHint {
+  uint32_t id, pu, pv;
+};
+
 // One patch against one ray: depth-first closest-first traversal of the binary
 // tree of subdomains, processed with an explicit stack (Sec. 3.3, Alg. 3).
 //   * each visited node splits its grid at 1/2 along its axis and tests both
@@ -356,7 +365,7 @@ struct Frame {
 };
 
 static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Best& best,
-                            Counters& c, std::vector<Split>* trace) {
+                            Counters& c, std::vector<Split>* trace, const OrderHint* hint = nullptr) {
   const int leaf_depth = 2 * L;
   std::vector<Frame> stack;
   stack.reserve(2 * leaf_depth + 4);
@@ -403,6 +412,8 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
     uint32_t csu = f.axis == 0 ? f.su / 2 : f.su, csv = f.axis == 1 ? f.sv / 2 : f.sv;
     uint32_t rpu = f.axis == 0 ? f.pu + csu : f.pu, rpv = f.axis == 1 ? f.pv + csv : f.pv;
     bool first_r = hr && (!hl || tr < tl);
+    if (hint && hint->id == id && hl && hr && f.depth + 1 != leaf_depth)
+      first_r = f.axis == 0 ? hint->pu >= rpu : hint->pv >= rpv;
     if (f.depth + 1 == leaf_depth) {
       double t = first_r ? tr : tl;
       if (better(t, id, best)) {
@@ -539,7 +550,7 @@ static int build_node(Scene& S, uint32_t first, uint32_t count) {
   return idx;
 }
 
-static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
+static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c, const OrderHint* hint = nullptr) {
   best.t = r.tmax;
   best.id = kNoHit;
   best.u = best.v = 0.0;
@@ -550,7 +561,7 @@ static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
       if (!slab(r, S.patches[k].lo, S.patches[k].hi, best.t, &e)) continue;
       c.cand++;
       c.cand_greg += S.patches[k].gregory;
-      intersect_patch(work_patch(S, k), k, work_ray(S, k, r), S.L, best, c, nullptr);
+      intersect_patch(work_patch(S, k), k, work_ray(S, k, r), S.L, best, c, nullptr, hint);
     }
     return;
   }
@@ -568,7 +579,7 @@ static void trace_ray(const Scene& S, const Ray& r, Best& best, Counters& c) {
         if (!slab(r, S.patches[id].lo, S.patches[id].hi, best.t, &e)) continue;
         c.cand++;
         c.cand_greg += S.patches[id].gregory;
-        intersect_patch(work_patch(S, id), id, work_ray(S, id, r), S.L, best, c, nullptr);
+        intersect_patch(work_patch(S, id), id, work_ray(S, id, r), S.L, best, c, nullptr, hint);
       }
       continue;
     }
@@ -900,6 +911,33 @@ void orc_intersect(void* s, const float* rays, uint32_t n, int nthreads, double*
       o[0] = c.node; o[1] = c.cand; o[2] = c.split; o[3] = c.backtrack;
       o[4] = c.greg; o[5] = c.leaf; o[6] = c.crop; o[7] = c.cand_greg;
     }
+  });
+}
+
+// orc_intersect with the hindsight order (OrderHint) on each ray's hinted patch:
+// hint_id, hint_u, hint_v are a closest hit of the ray (0xFFFFFFFF: no hint), e.g.
+// orc_intersect's own.  Measurement of the best case of a learned child order.
+void orc_intersect_hinted(void* s, const float* rays, uint32_t n, int nthreads, const uint32_t* hint_id,
+                          const double* hint_u, const double* hint_v, double* t, uint32_t* id, double* u, double* v,
+                          uint32_t* counters) {
+  const Scene& S = *(Scene*)s;
+  const uint32_t leaf = kFull >> S.L;
+  parallel_for(n, nthreads, [&](uint32_t i) {
+    Ray r = load_ray(rays + 8 * (size_t)i);
+    Best b;
+    Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
+    OrderHint h;
+    h.id = hint_id[i];
+    h.pu = std::min((uint32_t)(hint_u[i] / kUnit) & ~(leaf - 1), kFull - leaf);
+    h.pv = std::min((uint32_t)(hint_v[i] / kUnit) & ~(leaf - 1), kFull - leaf);
+    trace_ray(S, r, b, c, h.id == kNoHit ? nullptr : &h);
+    t[i] = b.t;
+    id[i] = b.id;
+    u[i] = b.u;
+    v[i] = b.v;
+    uint32_t* o = counters + 8 * (size_t)i;
+    o[0] = c.node; o[1] = c.cand; o[2] = c.split; o[3] = c.backtrack;
+    o[4] = c.greg; o[5] = c.leaf; o[6] = c.crop; o[7] = c.cand_greg;
   });
 }
 
