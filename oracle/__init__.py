@@ -47,8 +47,8 @@ def lib():
         L.orc_scene_nodes.argtypes = [vp]
         L.orc_scene_nodes.restype = u32
         L.orc_intersect.argtypes = [vp, P(C.c_float), u32, i32, P(d), P(u32), P(d), P(d), P(u32)]
-        L.orc_intersect_hinted.argtypes = [vp, P(C.c_float), u32, i32, P(u32), P(d), P(d), P(d), P(u32), P(d),
-                                           P(d), P(u32)]
+        L.orc_intersect_hinted.argtypes = [vp, P(C.c_float), u32, i32, i32, P(u32), P(d), P(d), P(d), P(u32),
+                                           P(d), P(d), P(u32)]
         L.orc_trace_patch.argtypes = [vp, u32, P(C.c_float), d, P(u32), i32, P(d)]
         L.orc_trace_patch.restype = i32
         L.orc_trace_patch_alg3.argtypes = [vp, u32, P(C.c_float), d, P(u32), i32, P(d)]
@@ -170,19 +170,22 @@ class Scene:
             out["counters"] = cnt
         return out
 
-    def intersect_hinted(self, rays, hint, nthreads: int = 0):
-        """Closest hits and counters with the hindsight child order on each ray's hinted
-        patch (hint: a dict(id, u, v) of closest hits, e.g. intersect's own): where both
-        halves of a split are hit, the half holding the hinted leaf goes first.  Bounds
-        what a learned child order can save."""
+    def intersect_hinted(self, rays, hint=None, nthreads: int = 0, lookahead: bool = False):
+        """Closest hits and counters in another child order, to bound what a learned order
+        can save.  Where both halves of a split are hit (not the leaf pair): with a hint
+        (a dict(id, u, v) of closest hits, e.g. intersect's own) the half holding the
+        hinted leaf goes first on the hinted patch (hindsight); with lookahead, on every
+        patch, the half whose first visit costs fewer split steps over the node's subtree."""
         r = np.ascontiguousarray(rays, dtype=np.float32).reshape(-1, 8)
         n = r.shape[0]
+        if hint is None:
+            hint = dict(id=np.full(n, NO_HIT, np.uint32), u=np.zeros(n), v=np.zeros(n))
         hid = np.ascontiguousarray(hint["id"], dtype=np.uint32)
         hu, hv = _f64(hint["u"]), _f64(hint["v"])
         t, u, v = np.zeros(n), np.zeros(n), np.zeros(n)
         ids = np.zeros(n, dtype=np.uint32)
         cnt = np.zeros((n, 8), dtype=np.uint32)
-        lib().orc_intersect_hinted(self._h, _p(r, C.c_float), n, nthreads, _p(hid, C.c_uint32),
+        lib().orc_intersect_hinted(self._h, _p(r, C.c_float), n, nthreads, int(lookahead), _p(hid, C.c_uint32),
                                    _p(hu, C.c_double), _p(hv, C.c_double), _p(t, C.c_double),
                                    _p(ids, C.c_uint32), _p(u, C.c_double), _p(v, C.c_double),
                                    _p(cnt, C.c_uint32))

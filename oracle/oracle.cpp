@@ -336,12 +336,18 @@ struct Split {
   uint32_t pu, pv, su, sv;
 };
 
-// Hindsight order (measurement only): the patch and leaf corner (units of 2^-23) of
-// a ray's known closest hit.  On that patch, wherever both halves of a split are
-// hit and they are not the leaf pair, the half holding that leaf is visited first
-// instead of the closer one: the ordering a perfect predictor of the final leaf
-// would give, to bound what any learned child order can save.
+// Orders other than closest-first, for measurement only (what a learned child order
+// could save at best); wherever both halves of a split are hit and they are not the
+// leaf pair:
+//   kHindsight: on the patch of the ray's known closest hit (id, leaf corner pu, pv
+//               in units of 2^-23), the half holding that leaf is visited first: the
+//               order a perfect predictor of the final leaf gives;
+//   kLookahead: on every patch, the half whose first visit costs fewer split steps
+//               over the node's subtree (both orders tried, closest-first below):
+//               the order a perfect predictor of that work label gives.
+enum OrderMode { kHindsight = 0, kLookahead = 1 };
 struct OrderHint {
+  int mode;
   uint32_t id, pu, pv;
 };
 
@@ -364,6 +370,38 @@ struct Frame {
   V3 d;
 };
 
+static void run_frames(const Patch& P, uint32_t id, const Ray& r, int L, Best& best, Counters& c,
+                       std::vector<Split>* trace, const OrderHint* hint, std::vector<Frame>& stack);
+
+// The two children of frame f (first = ch[0]) in the order first_r gives; the first
+// one gets its Gregory grid (the recompute of Alg. 3), the second is pushed for later.
+static void push_children(const Patch& P, const Frame& f, const Grid& gl, const Grid& gr, bool hl, bool hr,
+                          bool first_r, uint32_t rpu, uint32_t rpv, uint32_t csu, uint32_t csv, Counters& c,
+                          std::vector<Frame>& stack) {
+  Frame ch[2];
+  for (int k = 0; k < 2; ++k) {
+    bool is_r = (k == 0) ? first_r : !first_r;
+    Frame& n = ch[k];
+    n.pu = is_r ? rpu : f.pu;
+    n.pv = is_r ? rpv : f.pv;
+    n.su = csu;
+    n.sv = csv;
+    n.axis = 1 - f.axis;
+    n.depth = f.depth + 1;
+    n.second = (k == 1);
+    n.g = is_r ? gr : gl;
+    n.d = {0, 0, 0};
+  }
+  if (hl && hr) stack.push_back(ch[1]);
+  if (P.gregory) {  // the chosen child gets its own lower grid and displacement
+    Bound b = calc_points_and_d_int(P, ch[0].pu, ch[0].pv, ch[0].su, ch[0].sv);
+    c.greg++;
+    ch[0].g = b.q;
+    ch[0].d = b.d;
+  }
+  stack.push_back(ch[0]);
+}
+
 static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Best& best,
                             Counters& c, std::vector<Split>* trace, const OrderHint* hint = nullptr) {
   const int leaf_depth = 2 * L;
@@ -385,6 +423,12 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
     root.d = {0, 0, 0};
   }
   stack.push_back(root);
+  run_frames(P, id, r, L, best, c, trace, hint, stack);
+}
+
+static void run_frames(const Patch& P, uint32_t id, const Ray& r, int L, Best& best, Counters& c,
+                       std::vector<Split>* trace, const OrderHint* hint, std::vector<Frame>& stack) {
+  const int leaf_depth = 2 * L;
   while (!stack.empty()) {
     Frame f = stack.back();
     stack.pop_back();
@@ -412,8 +456,20 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
     uint32_t csu = f.axis == 0 ? f.su / 2 : f.su, csv = f.axis == 1 ? f.sv / 2 : f.sv;
     uint32_t rpu = f.axis == 0 ? f.pu + csu : f.pu, rpv = f.axis == 1 ? f.pv + csv : f.pv;
     bool first_r = hr && (!hl || tr < tl);
-    if (hint && hint->id == id && hl && hr && f.depth + 1 != leaf_depth)
+    if (hint && hint->mode == kHindsight && hint->id == id && hl && hr && f.depth + 1 != leaf_depth)
       first_r = f.axis == 0 ? hint->pu >= rpu : hint->pv >= rpv;
+    if (hint && hint->mode == kLookahead && hl && hr && f.depth + 1 != leaf_depth) {
+      uint32_t steps[2];
+      for (int o = 0; o < 2; ++o) {  // o = 0: closest first; o = 1: the other half first
+        std::vector<Frame> sub;
+        Best b2 = best;
+        Counters c2 = {0, 0, 0, 0, 0, 0, 0, 0};
+        push_children(P, f, gl, gr, hl, hr, o == 0 ? first_r : !first_r, rpu, rpv, csu, csv, c2, sub);
+        run_frames(P, id, r, L, b2, c2, nullptr, nullptr, sub);
+        steps[o] = c2.split;
+      }
+      if (steps[1] < steps[0]) first_r = !first_r;
+    }
     if (f.depth + 1 == leaf_depth) {
       double t = first_r ? tr : tl;
       if (better(t, id, best)) {
@@ -426,28 +482,7 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
       }
       continue;
     }
-    Frame ch[2];
-    for (int k = 0; k < 2; ++k) {
-      bool is_r = (k == 0) ? first_r : !first_r;
-      Frame& n = ch[k];
-      n.pu = is_r ? rpu : f.pu;
-      n.pv = is_r ? rpv : f.pv;
-      n.su = csu;
-      n.sv = csv;
-      n.axis = 1 - f.axis;
-      n.depth = f.depth + 1;
-      n.second = (k == 1);
-      n.g = is_r ? gr : gl;
-      n.d = {0, 0, 0};
-    }
-    if (hl && hr) stack.push_back(ch[1]);
-    if (P.gregory) {  // the chosen child gets its own lower grid and displacement
-      Bound b = calc_points_and_d_int(P, ch[0].pu, ch[0].pv, ch[0].su, ch[0].sv);
-      c.greg++;
-      ch[0].g = b.q;
-      ch[0].d = b.d;
-    }
-    stack.push_back(ch[0]);
+    push_children(P, f, gl, gr, hl, hr, first_r, rpu, rpv, csu, csv, c, stack);
   }
 }
 
@@ -914,10 +949,11 @@ void orc_intersect(void* s, const float* rays, uint32_t n, int nthreads, double*
   });
 }
 
-// orc_intersect with the hindsight order (OrderHint) on each ray's hinted patch:
-// hint_id, hint_u, hint_v are a closest hit of the ray (0xFFFFFFFF: no hint), e.g.
-// orc_intersect's own.  Measurement of the best case of a learned child order.
-void orc_intersect_hinted(void* s, const float* rays, uint32_t n, int nthreads, const uint32_t* hint_id,
+// orc_intersect in another child order (OrderHint, measurement of what a learned
+// order could save): mode kHindsight with hint_id, hint_u, hint_v a closest hit of
+// each ray (0xFFFFFFFF: none), e.g. orc_intersect's own; mode kLookahead ignores the
+// hints.
+void orc_intersect_hinted(void* s, const float* rays, uint32_t n, int nthreads, int mode, const uint32_t* hint_id,
                           const double* hint_u, const double* hint_v, double* t, uint32_t* id, double* u, double* v,
                           uint32_t* counters) {
   const Scene& S = *(Scene*)s;
@@ -927,10 +963,11 @@ void orc_intersect_hinted(void* s, const float* rays, uint32_t n, int nthreads, 
     Best b;
     Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
     OrderHint h;
+    h.mode = mode;
     h.id = hint_id[i];
     h.pu = std::min((uint32_t)(hint_u[i] / kUnit) & ~(leaf - 1), kFull - leaf);
     h.pv = std::min((uint32_t)(hint_v[i] / kUnit) & ~(leaf - 1), kFull - leaf);
-    trace_ray(S, r, b, c, h.id == kNoHit ? nullptr : &h);
+    trace_ray(S, r, b, c, (mode == kHindsight && h.id == kNoHit) ? nullptr : &h);
     t[i] = b.t;
     id[i] = b.id;
     u[i] = b.u;
