@@ -404,9 +404,8 @@ static void push_children(const Patch& P, const Frame& f, const Grid& gl, const 
 
 static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Best& best,
                             Counters& c, std::vector<Split>* trace, const OrderHint* hint = nullptr) {
-  const int leaf_depth = 2 * L;
   std::vector<Frame> stack;
-  stack.reserve(2 * leaf_depth + 4);
+  stack.reserve(4 * L + 4);  // at most one pending sibling per level
   Frame root;
   root.pu = root.pv = 0;
   root.su = root.sv = kFull;
