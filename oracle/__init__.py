@@ -47,6 +47,7 @@ def lib():
         L.orc_scene_nodes.argtypes = [vp]
         L.orc_scene_nodes.restype = u32
         L.orc_intersect.argtypes = [vp, P(C.c_float), u32, i32, P(d), P(u32), P(d), P(d), P(u32)]
+        L.orc_intersect_f64.argtypes = [vp, P(d), u32, i32, P(d), P(u32), P(d), P(d)]
         L.orc_intersect_hinted.argtypes = [vp, P(C.c_float), u32, i32, i32, P(u32), P(d), P(d), P(d), P(u32),
                                            P(d), P(d), P(u32)]
         L.orc_trace_patch.argtypes = [vp, u32, P(C.c_float), d, P(u32), i32, P(d)]
@@ -169,6 +170,16 @@ class Scene:
         if counters:
             out["counters"] = cnt
         return out
+
+    def intersect_f64(self, rays, nthreads: int = 0):
+        """Closest hits of rays given in double precision (n, 8): dict(t, id, u, v)."""
+        r = np.ascontiguousarray(rays, dtype=np.float64).reshape(-1, 8)
+        n = r.shape[0]
+        t, u, v = np.zeros(n), np.zeros(n), np.zeros(n)
+        ids = np.zeros(n, dtype=np.uint32)
+        lib().orc_intersect_f64(self._h, _p(r, C.c_double), n, nthreads, _p(t, C.c_double), _p(ids, C.c_uint32),
+                                _p(u, C.c_double), _p(v, C.c_double))
+        return dict(t=t, id=ids, u=u, v=v)
 
     def intersect_hinted(self, rays, hint=None, nthreads: int = 0, lookahead: bool = False):
         """Closest hits and counters in another child order, to bound what a learned order

@@ -948,6 +948,28 @@ void orc_intersect(void* s, const float* rays, uint32_t n, int nthreads, double*
   });
 }
 
+// orc_intersect for rays given in double precision (n x 8 doubles), e.g. rays moved
+// off the fp32 grid by the parity gate's graze check.
+void orc_intersect_f64(void* s, const double* rays, uint32_t n, int nthreads, double* t, uint32_t* id, double* u,
+                       double* v) {
+  const Scene& S = *(Scene*)s;
+  parallel_for(n, nthreads, [&](uint32_t i) {
+    const double* r8 = rays + 8 * (size_t)i;
+    Ray r;
+    r.o = {r8[0], r8[1], r8[2]};
+    r.tmin = r8[3];
+    r.d = {r8[4], r8[5], r8[6]};
+    r.tmax = r8[7];
+    Best b;
+    Counters c = {0, 0, 0, 0, 0, 0, 0, 0};
+    trace_ray(S, r, b, c);
+    t[i] = b.t;
+    id[i] = b.id;
+    u[i] = b.u;
+    v[i] = b.v;
+  });
+}
+
 // orc_intersect in another child order (OrderHint, measurement of what a learned
 // order could save): mode kHindsight with hint_id, hint_u, hint_v a closest hit of
 // each ray (0xFFFFFFFF: none), e.g. orc_intersect's own; mode kLookahead ignores the

@@ -21,11 +21,14 @@ excused only when the paper's error model explains it:
              (silhouettes, box edges and corners).  Only the nearer answer can be
              excused this way: a grazed oracle leaf when the GPU missed it and
              reports a farther hit or none, a grazed GPU leaf when the oracle missed
-             it and reports a farther hit or none.  The oracle confirms it: the
-             ray moved sideways out of the oracle's grazed box (or into the GPU's)
-             by the margin and a little more must give the GPU's answer (the same
-             patch within the distance tolerance, or a miss), so that a GPU that
-             skipped a leaf whose neighbour the ray would then meet is not excused.
+             it and reports a farther hit or none.  The oracle confirms the first:
+             on the ray moved sideways (in double precision) just out of its grazed
+             box, or by twice the slack in one of eight directions across the ray,
+             it must give the GPU's answer (a match by the rule above, or a miss),
+             so that a GPU that skipped a leaf whose neighbour the ray would then
+             meet is not excused.  For the second (a
+             false positive of rounding size, which the method allows) the GPU's
+             distance must be where the ray meets its box grown by the slack.
              (The margin is measured across the ray because a leaf box is often
              thin: the path along the ray through a flat box is short wherever the
              ray crosses it.);
@@ -107,14 +110,26 @@ def _lateral_margin(ray, lo, hi):
     return (dist if inside else -dist), w
 
 
-def _moved_ray(ray, shift, t_ref, reach):
-    """The ray moved sideways by `shift` (world), its origin also moved along it to
-    parameter max(tmin, t_ref - reach) so that the fp32 record stays close to the
-    hit; returns (fp32 ray, parameter offset of the new origin)."""
+def _moved_ray(ray, shift):
+    """The ray (8 values {o, tmin, d, tmax}) moved sideways by `shift` (world), in
+    double precision."""
+    out = np.array(ray, dtype=np.float64)
+    out[:3] += shift
+    return out
+
+
+def _entry(ray, lo, hi):
+    """FP64 entry distance of the ray into the box [lo, hi] (inf if missed)."""
     o, d = np.asarray(ray[:3], np.float64), np.asarray(ray[4:7], np.float64)
-    s0 = max(float(ray[3]), t_ref - reach)
-    out = np.array([*(o + s0 * d + shift), 0.0, *d, float(ray[7]) - s0])
-    return out.astype(np.float32), s0
+    near, far = float(ray[3]), float(ray[7])
+    for a in range(3):
+        if d[a] == 0.0:
+            if o[a] < lo[a] or o[a] > hi[a]:
+                return np.inf
+            continue
+        t0, t1 = (lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]
+        near, far = max(near, min(t0, t1)), min(far, max(t0, t1))
+    return near if near <= far else np.inf
 
 
 def _in_frame(osc, pid, ray):
@@ -198,23 +213,31 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
                         mgn, w = _lateral_margin(rf, lo, hi)
                         if abs(mgn) > slack:
                             continue
-                        # confirm with the oracle itself: the ray moved sideways out of the
-                        # oracle's grazed box (into the GPU's grazed box) by the margin and a
-                        # little more must give the GPU's answer
-                        reach = 4.0 * diag / float(np.linalg.norm(ray[4:7].astype(np.float64)))
-                        o2 = ray[:3].astype(np.float64) + max(float(ray[3]), t - reach) * ray[4:7]
-                        extra = slack + 16.0 * 2.0 ** -24 * float(np.abs(o2).max())
                         if side == "oracle":
-                            step = (mgn + extra) if mgn >= 0.0 else -extra
+                            # the GPU missed a leaf the ray grazes: the oracle itself must give
+                            # the GPU's answer for the ray moved sideways (in double precision)
+                            # just out of that box, or by twice the slack in one of eight
+                            # directions across the ray (a ray through a corner that boxes
+                            # share leaves all of them only in some directions)
+                            dn = rf[4:7] / np.linalg.norm(rf[4:7])
+                            a1 = np.cross(dn, w)
+                            a1 /= np.linalg.norm(a1)
+                            moves = [((mgn + slack) if mgn >= 0.0 else -slack) * w]
+                            moves += [2.0 * slack * (np.cos(th) * w + np.sin(th) * a1)
+                                      for th in np.arange(8) * (np.pi / 4)]
+                            o2r = osc.intersect_f64(np.array([_moved_ray(ray, R.T @ mv) for mv in moves]))
+                            if not g_hit[k]:
+                                agree = bool(np.any(o2r["id"] == NO_HIT))
+                            else:  # a match by the gate's own rule
+                                agree = bool(np.any((o2r["id"] == gid[k]) & (np.abs(o2r["t"] - gt[k]) <= tol_t) &
+                                                    (np.abs(o2r["u"] - gpu[k, 2]) <= tol_uv) &
+                                                    (np.abs(o2r["v"] - gpu[k, 3]) <= tol_uv)))
                         else:
-                            step = (-mgn + extra) if mgn < 0.0 else -extra
-                        r2, s0 = _moved_ray(ray, R.T @ (step * w), t, reach)
-                        o2r = osc.intersect(r2[None])
-                        t2, id2 = float(o2r["t"][0]) + s0, int(o2r["id"][0])
-                        if not g_hit[k]:
-                            agree = id2 == NO_HIT
-                        else:
-                            agree = id2 == int(gid[k]) and abs(t2 - gt[k]) <= tol_t
+                            # the GPU hit a leaf box the ray grazes (a false positive of
+                            # rounding size, which the method allows): its distance must be
+                            # where the ray meets that box grown by the slack
+                            e2 = _entry(rf, lo - slack, hi + slack)
+                            agree = np.isfinite(e2) and abs(e2 - gt[k]) <= tol_t
                         if agree:
                             kind = "graze"
                             break

@@ -38,7 +38,7 @@ def test_planted_errors_are_hard(c1, c1_oracle):
             g[hit, 0] = np.inf
             g[hit, 1] = np.array([O.NO_HIT], np.uint32).view(np.float32)[0]
         rep = gate(g, o, rays, c1_oracle, c1.diameter, L)
-        assert not rep["ok"] and rep["excused"]["hard"] >= 0.9 * len(hit), (kind, rep["excused"])
+        assert not rep["ok"] and rep["excused"]["hard"] == len(hit), (kind, rep["excused"])
 
 
 def test_tangent_excuse_is_limited_to_grazing_rays(c1, c1_oracle):
