@@ -80,6 +80,15 @@ def algorithmic_ops(cnt: np.ndarray) -> float:
     return float(ops)
 
 
+def roofline_record(ops_per_launch: float, launch_ms: float, kernel: str) -> dict:
+    """VALU roofline of one intersection launch: algorithmic lane-ops per launch over
+    the launch's measured duration, against 256 CUs x 64 lanes x 2.4 GHz."""
+    achieved = ops_per_launch / (launch_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2), "unit": "TOP/s",
+            "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None, "kernel": kernel,
+            "kernel_avg_ms": round(launch_ms, 4), "ops_per_launch": ops_per_launch}
+
+
 def traffic_from_profiles(kernel: str):
     """HBM bytes per launch of `kernel` measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE),
     scaled by the copy-kernel calibration, when recorded for the current kernel sources."""
@@ -151,15 +160,16 @@ def main():
     ap.add_argument("--no-counters", action="store_true", help="skip the counted launch (roofline)")
     ap.add_argument("--launch", default="",
                     help="waves_per_cu,fetch_min,traverse_min,grid_min,traverse_steps (default: library's)")
-    ap.add_argument("--only", choices=["", "plain", "batched", "learned"], default="",
+    ap.add_argument("--only", choices=["", "plain", "batched", "learned", "single"], default="",
                     help="time one variant only (a profiler run then sees one launch shape)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="batched variant with the given/default launch instead of the tuned one")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--world-frames", action="store_true",
                     help="subdivide in world coordinates instead of patch-local frames (Sec. 3.4)")
-    ap.add_argument("--policy-rays", type=int, default=1 << 20,
-                    help="secondary rays on the 512-patch torus whose records train the ordering network")
+    ap.add_argument("--policy-rays", type=int, default=12 << 20,
+                    help="secondary rays on the 512-patch torus whose records train the ordering network "
+                         "(12 x 2^20 rays give about 10M labelled records)")
     ap.add_argument("--policy-steps", type=int, default=4000, help="Adam steps of the ordering network")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer once (a plain copy kernel of known size that "
@@ -308,6 +318,38 @@ def main():
             "kernel_ms": float(np.mean(laps)), "note": "closest-first, both classes in one launch, world frame"}
         log(f"batched, world frame: {ms:.3f} ms/step -> {variants['batched_world_frames']['mrays_per_s']:.1f} MRays/s")
         del wsc, wh, wb
+    single_hits = None
+    if args.only in ("", "single"):
+        # the ablation of Sec. 3.3's two-box test: each step tests only the current
+        # domain's box (same launch parameters as the batched variant)
+        ssc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth,
+                        local_frames=not args.world_frames, single_box=True)
+        ssc.set_launch(**{k: v for k, v in scene.get_launch().items() if k != "waves_per_cu"})
+        sh = [torch.empty_like(hp), torch.empty_like(hd)]
+        sb = [(0, prim, sh[0]), (0, diff, sh[1])]
+
+        def single_step(evs=None):
+            if evs:
+                evs[0].record(stream)
+            ssc.intersect_batched(sb)
+            if evs:
+                evs[1].record(stream)
+
+        laps, ms = timed(single_step, 2)
+        single_hits = (sh[0].cpu().numpy(), sh[1].cpu().numpy())
+        v = {"ms_per_step": ms, "mrays_per_s": (n_p + n_d) / (ms * 1e-3) / 1e6, "launches_per_step": 1,
+             "kernel_ms": float(np.mean(laps)),
+             "note": "ablation (Sec. 3.3): each step tests only the current domain's box; closest-first "
+                     "variant's launch parameters, both classes in one launch"}
+        if not args.no_counters:
+            _, sc_p = ssc.intersect_counted(prim)
+            _, sc_d = ssc.intersect_counted(diff)
+            sc_p, sc_d = sc_p.cpu().numpy(), sc_d.cpu().numpy()
+            v["work_per_ray"] = {c: {"primary": float(sc_p[:, k].mean()), "diffuse": float(sc_d[:, k].mean())}
+                                 for k, c in enumerate(COUNTERS)}
+        variants["batched_single_box"] = v
+        log(f"batched, single box per step: {ms:.3f} ms/step -> {v['mrays_per_s']:.1f} MRays/s")
+        del ssc, sh, sb
     bounce = None
     if args.only == "":
         # secondary rays as the 1M configuration states them: one cosine bounce per primary
@@ -450,6 +492,11 @@ def main():
                        w.diameter, w.leaf_depth, label="bounce-launch primary")
             variants["batched_bounce"]["parity_sample"] = {"bounce": summary(rb), "primary": summary(rbp)}
             gates["batched_bounce"] = rb["ok"] and rbp["ok"]
+        if single_hits is not None:
+            sp_ = gate(single_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="1box-primary")
+            sd_ = gate(single_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="1box-diffuse")
+            variants["batched_single_box"]["parity_sample"] = {"primary": summary(sp_), "diffuse": summary(sd_)}
+            gates["batched_single_box"] = sp_["ok"] and sd_["ok"]
         if learned_hits is not None:
             lp_ = gate(learned_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="l-primary")
             ld_ = gate(learned_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="l-diffuse")
@@ -574,10 +621,16 @@ def train_policy(args, torch, ccs, scenes):
                    local_frames=not args.world_frames)
 
     def records(r_np):
-        r = torch.from_numpy(r_np).cuda()
-        f, y = g1.record(r, g1.intersect(r))
-        keep = (y != ccs.NO_LABEL).nonzero().squeeze(1)
-        return f[keep].contiguous(), y[keep].contiguous()
+        # in chunks of 2^20 rays: a ray gives L rows before the unlabelled ones are dropped
+        fs, ys = [], []
+        for b in range(0, len(r_np), 1 << 20):
+            r = torch.from_numpy(r_np[b:b + (1 << 20)]).cuda()
+            f, y = g1.record(r, g1.intersect(r))
+            keep = (y != ccs.NO_LABEL).nonzero().squeeze(1)
+            fs.append(f[keep].contiguous())
+            ys.append(y[keep].contiguous())
+            del f, y, r
+        return torch.cat(fs), torch.cat(ys)
 
     f, y = records(rays)
     th = torch.from_numpy(scenes.mlp_init()).cuda()
@@ -648,6 +701,20 @@ def bench_animation(args, torch, ccs, scenes):
     ms = ev[0].elapsed_time(ev[-1]) / args.steps
     value = n_rays / (ms * 1e-3) / 1e6
     log(f"animation: {ms:.3f} ms per replay of {nf} refits + one launch -> {value:.1f} MRays/s")
+    roofline = None
+    if not args.no_counters:
+        # the intersection launch of the replay, timed eagerly on the refit frames, and
+        # its algorithmic work from the counting kernel on the same batches
+        kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for e0, e1 in kev:
+            e0.record()
+            scene.intersect_batched(batches)
+            e1.record()
+        _, cnt = scene.intersect_batched(batches, counted=True)
+        torch.cuda.synchronize()
+        kms = float(np.median([e0.elapsed_time(e1) for e0, e1 in kev]))
+        roofline = roofline_record(algorithmic_ops(cnt.cpu().numpy()), kms, "k_trace<false, false>")
+        log(f"animation intersect launch {kms:.3f} ms, roofline {roofline['frac']}")
 
     cpu, parity = None, None
     if not args.no_cpu_baseline:
@@ -681,7 +748,7 @@ def bench_animation(args, torch, ccs, scenes):
                    "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
                    "launch": scene.get_launch(), "autotuned": tuned is not None, "leaf_depth": a.leaf_depth,
                    "ms_median": float(np.median(laps))},
-        "roofline": None, "cpu_baseline": cpu, "parity_sample": parity, "source_hash": source_hash()}),
+        "roofline": roofline, "cpu_baseline": cpu, "parity_sample": parity, "source_hash": source_hash()}),
         flush=True)
 
 
@@ -751,11 +818,30 @@ def bench_combined(args, torch, ccs, scenes):
         log(f"{label}: {ms:.1f} ms/step -> {res['mrays_per_s']:.1f} MRays/s; levels {[round(t, 2) for t in lvl]} ms")
         return res
 
+    def level_ops():
+        """Algorithmic work of each level's launch (counting kernel, same batches as the
+        last timed step)."""
+        ops = []
+        for b in range(B + 1):
+            _, cnt = scene.intersect_batched([(f, rays[b][f], hits[b][f]) for f in range(F)], counted=True)
+            ops.append(algorithmic_ops(cnt.cpu().numpy()))
+            del cnt
+        return ops
+
+    def with_roofline(res, kname):
+        if not args.no_counters:
+            ops = level_ops()
+            tot_ms = sum(res["intersect_ms_per_level"])
+            res["roofline"] = roofline_record(sum(ops) / (B + 1), tot_ms / (B + 1), kname)
+            res["roofline"]["per_level_frac"] = [round(o / (t * 1e-3) / 1e12 / PEAK_VALU_TOPS, 4)
+                                                 for o, t in zip(ops, res["intersect_ms_per_level"])]
+        return res
+
     variants = {}
     b0 = [(f, rays[0][f], hits[0][f]) for f in range(F)]
     if args.autotune:
         autotune.tuned(scene, b0, name=w.name)
-    variants["batched"] = run("closest-first")
+    variants["batched"] = with_roofline(run("closest-first"), "k_trace<false, false>")
     h_plain = [[hits[b][f][:4096].cpu().numpy() for f in (0, F - 1)] for b in range(B + 1)]
     samples = [[rays[b][f][:4096].cpu().numpy() for f in (0, F - 1)] for b in range(B + 1)]
     if info["bvh_depth"] < 37:
@@ -763,7 +849,7 @@ def bench_combined(args, torch, ccs, scenes):
         scene.set_policy(policy)
         if args.autotune:
             autotune.tuned(scene, b0, name=w.name, learned=True)
-        variants["learned_batched"] = run("learned order")
+        variants["learned_batched"] = with_roofline(run("learned order"), "k_trace<false, true>")
         variants["learned_batched"]["policy"] = pstats
         scene.set_policy(None)
     cpu, parity = None, None
@@ -799,7 +885,7 @@ def bench_combined(args, torch, ccs, scenes):
                                f"per frame ({F * (B + 1) * n} rays per step)", "leaf_depth": w.leaf_depth,
                    "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
                    "variant": "closest-first order, batched over frames"},
-        "variants": variants, "roofline": None, "cpu_baseline": cpu, "parity_sample": parity,
+        "variants": variants, "roofline": variants[head].get("roofline"), "cpu_baseline": cpu, "parity_sample": parity,
         "device_memory_gib": {"scene_all_frames": round(info["device_bytes"] / 2**30, 3),
                               "frame_control_points": round(sum(c.numel() * 4 for c in cps) / 2**30, 3),
                               "rays": round(ray_bytes / 2**30, 3), "hits": round(hit_bytes / 2**30, 3)},

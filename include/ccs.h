@@ -59,6 +59,16 @@ extern "C" {
  * neighbours; Sec. 3.4 closes them by growing boxes).  The BVH stays in world
  * space.  Frames follow the geometry on refit. */
 #define CCS_FLAG_LOCAL_FRAMES 1u
+/* Scene flag, for measurement only: each step of Alg. 3 tests only the box of the
+ * current domain (its grid's hull, grown by the domain's own displacement for a
+ * Gregory patch) instead of the two child boxes of Sec. 3.3; a hit box above the
+ * leaf depth is split and its lower half entered with the upper half pending, a
+ * missed one backtracks, and a hit leaf box is recorded at its own entry distance.
+ * Sec. 3.3 reports that the two-box test nearly halves the traversal time against
+ * this.  Results obey the same contract (closest leaf box hit; a Gregory leaf box
+ * is then the leaf's own bound).  Closest-first only: ccs_scene_set_policy
+ * returns CCS_ERR_UNSUPPORTED on such a scene. */
+#define CCS_FLAG_SINGLE_BOX 2u
 
 typedef enum ccs_status {
   CCS_OK = 0,
@@ -95,7 +105,7 @@ typedef struct ccs_scene_desc {
   uint32_t n_patches;           /* 0 <= n < 2^31; an empty scene makes every ray miss */
   int32_t location;             /* CCS_HOST or CCS_DEVICE */
   uint32_t leaf_depth;          /* L, 1..16 */
-  uint32_t flags;               /* 0 or CCS_FLAG_LOCAL_FRAMES */
+  uint32_t flags;               /* 0, or CCS_FLAG_LOCAL_FRAMES and/or CCS_FLAG_SINGLE_BOX */
   void* stream;                 /* hipStream_t used for the uploads */
 } ccs_scene_desc;
 
@@ -163,6 +173,13 @@ typedef struct ccs_batch {
 ccs_status ccs_intersect_batched(const ccs_scene* scene, const ccs_batch* batches, uint32_t n_batches,
                                  void* stream);
 
+/* As ccs_intersect_batched, with the per-ray work counters of
+ * ccs_intersect_counted: counters (device, 8 uint32 per ray) row k belongs to ray
+ * k of the launch, the batches' rays taken in order (batch 0's first).  The same
+ * separately compiled counting kernel; used for measurement. */
+ccs_status ccs_intersect_batched_counted(const ccs_scene* scene, const ccs_batch* batches, uint32_t n_batches,
+                                         uint32_t* counters, void* stream);
+
 /* Closest hits of n rays (Alg. 3 per candidate patch, candidates from the BVH
  * nearest first, the best distance so far pruning both).  rays and hits are
  * device pointers owned by the caller; n == 0 is a no-op.  Asynchronous on
@@ -222,6 +239,26 @@ ccs_status ccs_bounce(const ccs_scene* scene, const ccs_ray* rays, const ccs_hit
  * outside the scene's frames. */
 ccs_status ccs_bounce_frame(const ccs_scene* scene, uint32_t frame, const ccs_ray* rays, const ccs_hit* hits,
                             const float* uniforms, uint32_t n, ccs_ray* out_rays, void* stream);
+
+/* Measurement of the fp32 grid arithmetic (Sec. 3.4 compares control points
+ * recomputed for a subdomain with those reached by repeated subdivision).  For
+ * query k: patch patch_ids[k] (index into the creation arrays), the subdomain
+ * reached by depths[k] splits (u first, alternating) whose halves are the bits of
+ * codes[k] (split s owns bit 2L-1-s, set for the upper half; no other bits set).
+ * out (n x CCS_DEBUG_GRID_FLOATS fp32) row k holds, as stored on `frame`
+ * (anchored, and mapped into the patch frame with CCS_FLAG_LOCAL_FRAMES):
+ *   [0, 60)    the patch's stored points: x, y, z of slots 0..15, then of the P^v;
+ *   [60, 108)  Alg. 2 (calcPointsAndD) on the subdomain as the intersection kernel
+ *              recomputes it: component c of grid point (i, j) at 60 + 16c + 4j + i;
+ *   [108, 111) its displacement d (0 for a Bezier patch);
+ *   [111, 159) Bezier patches: the stored grid split along the path by the
+ *              intersection kernel's split step (de Casteljau halves), same
+ *              layout; NaN for a Gregory patch (its grid is recomputed at every node);
+ *   [159]      0, or NaN for a query out of range (every value of its row is NaN).
+ * All pointers are device pointers; asynchronous on `stream`. */
+#define CCS_DEBUG_GRID_FLOATS 160
+ccs_status ccs_debug_grids(const ccs_scene* scene, uint32_t frame, const uint32_t* patch_ids, const uint32_t* codes,
+                           const uint32_t* depths, uint32_t n, float* out, void* stream);
 
 /* ---------------------------------------------------- learned child ordering
  * Alg. 3 visits the two halves of a split closest box first (Sec. 3.3).  A

@@ -31,7 +31,10 @@ excused only when the paper's error model explains it:
              distance must be where the ray meets its box grown by the slack.
              (The margin is measured across the ray because a leaf box is often
              thin: the path along the ray through a flat box is short wherever the
-             ray crosses it.);
+             ray crosses it.)  A GPU leaf box the ray starts outside of by at most
+             the slack, reported at tmin, is the same rounding-size false positive
+             (a secondary ray's origin sits a leaf-sized offset from the surface, and
+             at coordinates far from the origin fp32 rounds it by more);
   * tangent -- same patch, |dt| within tolerance, the ray within 1.2 degrees of
              tangent to the surface at the oracle's hit (|cos| < 0.02), and the
              surface at the GPU's (u, v) within the GPU leaf box's diagonal of the
@@ -212,7 +215,13 @@ def gate(gpu: np.ndarray, ora: dict, rays: np.ndarray, osc: "Scene", diameter: f
                         slack = 1e-3 * diag + 1e-7 * (abs(t) + 1.0)
                         mgn, w = _lateral_margin(rf, lo, hi)
                         if abs(mgn) > slack:
-                            continue
+                            # the GPU's leaf box may also be one the ray starts just outside
+                            # of: then it enters it at tmin by rounding alone, whatever the
+                            # ray's path across it
+                            p0 = rf[:3] + rf[3] * rf[4:7]
+                            gap = float(np.linalg.norm(np.maximum(lo - p0, 0.0) + np.maximum(p0 - hi, 0.0)))
+                            if not (side == "gpu" and 0.0 < gap <= slack and abs(t - rf[3]) <= tol_t):
+                                continue
                         if side == "oracle":
                             # the GPU missed a leaf the ray grazes: the oracle itself must give
                             # the GPU's answer for the ray moved sideways (in double precision)

@@ -19,6 +19,7 @@ CCS_OK, CCS_ERR_INVALID_ARG, CCS_ERR_OOM, CCS_ERR_HIP, CCS_ERR_UNSUPPORTED = ran
 CCS_BEZIER, CCS_GREGORY = 0, 1
 CCS_HOST, CCS_DEVICE = 0, 1
 CCS_FLAG_LOCAL_FRAMES = 1
+CCS_FLAG_SINGLE_BOX = 2
 NO_HIT = 0xFFFFFFFF
 COUNTER_NAMES = ("node", "cand", "split", "backtrack", "greg", "leaf", "crop", "cand_greg")
 
@@ -26,11 +27,13 @@ EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_coun
            "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
            "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched",
            "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train",
-           "ccs_bounce_frame", "ccs_device_bytes_in_use")
+           "ccs_bounce_frame", "ccs_device_bytes_in_use", "ccs_debug_grids",
+           "ccs_intersect_batched_counted")
 MAX_BATCHES = 32
 MAX_RAYS = (1 << 31) - 1  # per call
 POLICY_PARAMS = 1732
 NO_LABEL = 255
+DEBUG_GRID_FLOATS = 160
 
 
 class CcsError(RuntimeError):
@@ -96,12 +99,14 @@ def lib():
         L.ccs_scene_set_frames.argtypes = [vp, u32]
         L.ccs_refit_frame.argtypes = [vp, u32, vp, i32, vp]
         L.ccs_intersect_batched.argtypes = [vp, C.POINTER(Batch), u32, vp]
+        L.ccs_intersect_batched_counted.argtypes = [vp, C.POINTER(Batch), u32, vp, vp]
         L.ccs_scene_get_launch.argtypes = [vp, C.POINTER(LaunchParams)]
         L.ccs_scene_set_policy.argtypes = [vp, vp, vp]
         L.ccs_policy_record.argtypes = [vp, vp, vp, u32, vp, vp, vp]
         L.ccs_policy_infer.argtypes = [vp, vp, u32, vp, vp]
         L.ccs_policy_grad.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
         L.ccs_policy_train.argtypes = [vp, vp, vp, u32, C.POINTER(TrainParams), C.POINTER(AdamState), vp, vp]
+        L.ccs_debug_grids.argtypes = [vp, u32, vp, vp, vp, u32, vp, vp]
         L.ccs_device_bytes_in_use.argtypes = []
         for name in EXPORTS:
             if name not in ("ccs_scene_destroy", "ccs_last_error", "ccs_device_bytes_in_use"):
@@ -132,9 +137,12 @@ class Scene:
 
     control_points: (n, 20, 3) float32 (torch tensor on cuda or cpu, or numpy);
     patch_types: (n,) uint8 (0 Bezier, 1 Gregory); leaf_depth: L in [1, 16].
+    local_frames: subdivide in patch-local frames; single_box: the one-box-per-step
+    ablation of Sec. 3.3 (measurement only).
     """
 
-    def __init__(self, control_points, patch_types, leaf_depth: int, stream=None, local_frames: bool = False):
+    def __init__(self, control_points, patch_types, leaf_depth: int, stream=None, local_frames: bool = False,
+                 single_box: bool = False):
         import torch
         cp = torch.as_tensor(control_points)
         ty = torch.as_tensor(patch_types)
@@ -152,7 +160,7 @@ class Scene:
         self.local_frames = bool(local_frames)
         desc = SceneDesc(cp.data_ptr() if self.n else None, ty.data_ptr() if self.n else None, self.n,
                          CCS_DEVICE if on_dev else CCS_HOST, self.leaf_depth,
-                         CCS_FLAG_LOCAL_FRAMES if local_frames else 0,
+                         (CCS_FLAG_LOCAL_FRAMES if local_frames else 0) | (CCS_FLAG_SINGLE_BOX if single_box else 0),
                          _stream(stream).value if on_dev else None)
         h = C.c_void_p()
         _check(lib().ccs_scene_create(C.byref(desc), C.byref(h)))
@@ -191,11 +199,12 @@ class Scene:
         _check(lib().ccs_refit_frame(self._h, int(frame), _ptr(cp), CCS_DEVICE if cp.is_cuda else CCS_HOST,
                                      _stream(stream)))
 
-    def intersect_batched(self, batches, stream=None):
+    def intersect_batched(self, batches, stream=None, counted: bool = False):
         """batches: list of (frame, rays (N, 8) cuda float32, hits (N, 4) cuda float32 or None).
-        Returns the list of hit tensors (one launch for all batches)."""
+        Returns the list of hit tensors (one launch for all batches), and with counted
+        also the (sum N, 8) int32 work counters of the launch's rays in batch order."""
         import torch
-        out, arr = [], (Batch * max(1, len(batches)))()
+        out, arr, total = [], (Batch * max(1, len(batches)))(), 0
         for k, (frame, rays, hits) in enumerate(batches):
             r = self._rays(rays)
             if hits is None:
@@ -203,8 +212,13 @@ class Scene:
             hits = _out(hits, r.shape[0], 4, torch.float32, "hits")
             arr[k] = Batch(int(frame), r.shape[0], r.data_ptr(), hits.data_ptr())
             out.append(hits)
-        _check(lib().ccs_intersect_batched(self._h, arr, len(batches), _stream(stream)))
-        return out
+            total += r.shape[0]
+        if not counted:
+            _check(lib().ccs_intersect_batched(self._h, arr, len(batches), _stream(stream)))
+            return out
+        cnt = torch.empty((total, 8), dtype=torch.int32, device="cuda")
+        _check(lib().ccs_intersect_batched_counted(self._h, arr, len(batches), _ptr(cnt), _stream(stream)))
+        return out, cnt
 
     def set_launch(self, waves_per_cu: int = 0, fetch_min: int = 16, traverse_min: int = 1, grid_min: int = 8,
                    traverse_steps: int = 3, decide_min: int = 8):
@@ -278,6 +292,20 @@ class Scene:
         cp = cp.contiguous()
         self._refit_keep = cp  # device input must outlive the queued work
         _check(lib().ccs_refit(self._h, _ptr(cp), CCS_DEVICE if cp.is_cuda else CCS_HOST, _stream(stream)))
+
+    def debug_grids(self, patch_ids, codes, depths, frame: int = 0, stream=None):
+        """Rows (N, DEBUG_GRID_FLOATS) float32 of ccs_debug_grids: stored points, the
+        recomputed grid and displacement, and the split-chain grid of each subdomain."""
+        import torch
+        q = [torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.uint32)).view(np.int32)).cuda()
+             for x in (patch_ids, codes, depths)]
+        n = q[0].numel()
+        if any(x.numel() != n for x in q):
+            raise ValueError("patch_ids, codes and depths must have the same length")
+        out = torch.empty((n, DEBUG_GRID_FLOATS), dtype=torch.float32, device=q[0].device)
+        _check(lib().ccs_debug_grids(self._h, int(frame), _ptr(q[0]), _ptr(q[1]), _ptr(q[2]), n, _ptr(out),
+                                     _stream(stream)))
+        return out
 
     def bounce(self, rays, hits, uniforms, out=None, stream=None, frame: int = 0):
         """Secondary rays from hits (uniforms: (N, 2) float32 in [0, 1)) on the given frame."""

@@ -242,7 +242,8 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
     return fail(CCS_ERR_INVALID_ARG, "leaf_depth must be in [1, 16]");
   if (desc->location != CCS_HOST && desc->location != CCS_DEVICE)
     return fail(CCS_ERR_INVALID_ARG, "location must be CCS_HOST or CCS_DEVICE");
-  if ((desc->flags & ~CCS_FLAG_LOCAL_FRAMES) != 0) return fail(CCS_ERR_UNSUPPORTED, "unknown flags");
+  if ((desc->flags & ~(CCS_FLAG_LOCAL_FRAMES | CCS_FLAG_SINGLE_BOX)) != 0)
+    return fail(CCS_ERR_UNSUPPORTED, "unknown flags");
 
   // host-side validation needs no GPU; device input is fetched first
   std::vector<float> cp;
@@ -326,6 +327,7 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
   D.n_patches = n;
   D.n_nodes = n_nodes;
   D.leaf_depth = (int)desc->leaf_depth;
+  D.single_box = (desc->flags & CCS_FLAG_SINGLE_BOX) != 0;
   float4* nodes = nullptr;
   uint32_t *perm = nullptr, *invp = nullptr, *lvl = nullptr;
   int32_t *lpar = nullptr, *npar = nullptr;
@@ -551,8 +553,8 @@ ccs_status ccs_intersect_counted(const ccs_scene* s, const ccs_ray* rays, uint32
   return launch_batches(s, one_batch(rays, n, hits), counters, stream);
 }
 
-ccs_status ccs_intersect_batched(const ccs_scene* s, const ccs_batch* batches, uint32_t n_batches, void* stream) {
-  g_error.clear();
+static ccs_status batched(const ccs_scene* s, const ccs_batch* batches, uint32_t n_batches, uint32_t* counters,
+                          void* stream) {
   if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
   if (n_batches == 0) return CCS_OK;
   if (!batches) return fail(CCS_ERR_INVALID_ARG, "batches is NULL");
@@ -574,7 +576,19 @@ ccs_status ccs_intersect_batched(const ccs_scene* s, const ccs_batch* batches, u
   if (total > kMaxRaysPerCall) return fail(CCS_ERR_INVALID_ARG, "more than 2^31 - 1 rays in one call");
   bt.prefix[n_batches] = (uint32_t)total;
   if (total == 0) return CCS_OK;
-  return launch_batches(s, bt, nullptr, stream);
+  return launch_batches(s, bt, counters, stream);
+}
+
+ccs_status ccs_intersect_batched(const ccs_scene* s, const ccs_batch* batches, uint32_t n_batches, void* stream) {
+  g_error.clear();
+  return batched(s, batches, n_batches, nullptr, stream);
+}
+
+ccs_status ccs_intersect_batched_counted(const ccs_scene* s, const ccs_batch* batches, uint32_t n_batches,
+                                         uint32_t* counters, void* stream) {
+  g_error.clear();
+  if (!counters) return fail(CCS_ERR_INVALID_ARG, "counters is NULL");
+  return batched(s, batches, n_batches, counters, stream);
 }
 
 ccs_status ccs_scene_set_launch(ccs_scene* s, const ccs_launch_params* p) {
@@ -591,7 +605,8 @@ ccs_status ccs_scene_get_launch(const ccs_scene* s, ccs_launch_params* p) {
   g_error.clear();
   if (!s || !p) return fail(CCS_ERR_INVALID_ARG, "scene or params is NULL");
   *p = s->launch;
-  if (p->waves_per_cu == 0) p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false, s->dev.policy.w != nullptr);
+  if (p->waves_per_cu == 0)
+    p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false, s->dev.policy.w != nullptr, s->dev.single_box);
   return CCS_OK;
 }
 
@@ -617,6 +632,20 @@ ccs_status ccs_bounce(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hi
   return ccs_bounce_frame(s, 0, rays, hits, uniforms, n, out_rays, stream);
 }
 
+ccs_status ccs_debug_grids(const ccs_scene* s, uint32_t frame, const uint32_t* patch_ids, const uint32_t* codes,
+                           const uint32_t* depths, uint32_t n, float* out, void* stream) {
+  g_error.clear();
+  if (!s) return fail(CCS_ERR_INVALID_ARG, "scene is NULL");
+  if (frame >= s->dev.n_frames) return fail(CCS_ERR_INVALID_ARG, "frame out of range");
+  if (n == 0) return CCS_OK;
+  if (!patch_ids || !codes || !depths || !out) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  ccs::DeviceScene f = s->dev;
+  f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
+  hipError_t e = ccs::launch_debug_grids(f, patch_ids, codes, depths, n, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "debug grid launch");
+  return CCS_OK;
+}
+
 // ------------------------------------------------------- learned child ordering
 ccs_status ccs_scene_set_policy(ccs_scene* s, const float* params, void* stream) {
   g_error.clear();
@@ -625,6 +654,7 @@ ccs_status ccs_scene_set_policy(ccs_scene* s, const float* params, void* stream)
     s->dev.policy = ccs::PolicyDev{nullptr, nullptr};
     return CCS_OK;
   }
+  if (s->dev.single_box) return fail(CCS_ERR_UNSUPPORTED, "the single-box ablation has no learned order");
   if (s->bvh_depth >= ccs::kMaxBvhDepthLearned)
     return fail(CCS_ERR_UNSUPPORTED, "BVH depth " + std::to_string(s->bvh_depth) +
                                          " exceeds the learned-order kernel's node stack");

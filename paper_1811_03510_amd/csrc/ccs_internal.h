@@ -41,6 +41,7 @@ struct DeviceScene {
   float4* frames;            // patch-local frames: 3 rows per record (per frame), row 0's w = the box pad;
                              // nullptr: world frame
   size_t frame_frames_f4;    // float4s per frame in frames (n_patches * 3)
+  bool single_box;           // Alg. 3 steps test only the current domain's box (ablation; closest first)
 };
 
 // Rays of one launch: up to kMaxBatches batches, each with its own frame, ray
@@ -70,7 +71,7 @@ struct LaunchParams {
 constexpr uint32_t kMaxBvhDepth = 48;
 constexpr uint32_t kMaxBvhDepthLearned = 32;
 
-int max_waves_per_cu(bool counted, bool learned);
+int max_waves_per_cu(bool counted, bool learned, bool single_box);
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
                             uint32_t waves_per_cu, hipStream_t stream);
 hipError_t launch_refit(const DeviceScene& s, const float* cp_world, const uint32_t* level_offsets,
@@ -88,6 +89,9 @@ hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* partia
                            float lr, float beta1, float beta2, float eps, float c1, float c2, float* loss,
                            hipStream_t stream);
 hipError_t launch_fill(float* p, uint32_t n, float value, hipStream_t stream);
+constexpr int kDebugGridFloats = 160;
+hipError_t launch_debug_grids(const DeviceScene& s, const uint32_t* patch, const uint32_t* code,
+                              const uint32_t* depth, uint32_t n, float* out, hipStream_t stream);
 hipError_t launch_bounce(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                          uint32_t n, ccs_ray* out, hipStream_t stream);
 

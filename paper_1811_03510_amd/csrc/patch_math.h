@@ -95,6 +95,24 @@ __device__ __forceinline__ void split_fold(const float g[4][4], float o, float i
   s.fb = fminf(s.fb, fmaxf(b0, b1));
 }
 
+// The box of one component of a whole grid, [min, max + d], folded into the
+// slab interval (na, fa) of s (the fields nb, fb are left alone).
+__device__ __forceinline__ void grid_fold(const float g[4][4], float o, float inv, float d, SlabPair& s) {
+  float lo = fminf(g[0][0], g[0][1]), hi = fmaxf(g[0][0], g[0][1]);
+  lo = fminf(fminf(lo, g[0][2]), g[0][3]);
+  hi = fmaxf(fmaxf(hi, g[0][2]), g[0][3]);
+#pragma unroll
+  for (int a = 1; a < 4; ++a) {
+    lo = fminf(fminf(lo, g[a][0]), g[a][1]);
+    lo = fminf(fminf(lo, g[a][2]), g[a][3]);
+    hi = fmaxf(fmaxf(hi, g[a][0]), g[a][1]);
+    hi = fmaxf(fmaxf(hi, g[a][2]), g[a][3]);
+  }
+  const float a0 = (lo - o) * inv, a1 = (hi + d - o) * inv;
+  s.na = fmaxf(s.na, fminf(a0, a1));
+  s.fa = fminf(s.fa, fmaxf(a0, a1));
+}
+
 // Chosen half written back transposed: new G[b][k] = point k of row b, the
 // second half taken mirrored (a3, m23, m123, m).
 __device__ __forceinline__ void take_half(const Row7 e[4], bool second, float g[4][4]) {

@@ -92,9 +92,16 @@ __device__ __forceinline__ void write_hit(const BatchTable& bt, uint32_t* __rest
 // Three waves per SIMD (at most 168 VGPRs): the closest-first variant fits by
 // itself; the learned variant is held to it (a few loop-invariant values of the
 // ray-fetch and leaf-record paths then live in scratch instead of registers).
-template <bool kStats, bool kLearned>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
-                                                  LaunchParams lp) {
+//
+// kSingle (the ablation of Sec. 3.3's two-box test, closest-first kernels only):
+// a step tests only the box of the current domain (the hull of its grid, grown by
+// its own displacement) and, when it is hit above the leaf depth, splits and
+// enters the lower half with the upper one pending; a missed box backtracks, and
+// a hit leaf box is recorded at its own entry distance.  No distance orders the
+// halves, and every pending half costs a grid recompute.
+template <bool kStats, bool kLearned, bool kSingle>
+__device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
+                                           LaunchParams lp) {
   constexpr int kStack = kLearned ? (int)kMaxBvhDepthLearned : (int)kMaxBvhDepth;
   __shared__ int stack[kStack * kBlock];
   // learned order, 16 words per lane: the node's corners and slab results from the
@@ -380,70 +387,111 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     // -------------------------------------------------- one subdivision step
     if (mode == kStep) {
       if (kStats) cnt.split++;
-      // split each component and fold its two child boxes into the slab test at once
-      Row7 ex[4], ey[4], ez[4];
-      SlabPair sp2 = {ptmin, __builtin_inff(), ptmin, __builtin_inff()};
-      split_fold(G.x, pox, pix, dx, ex, sp2);
-      split_fold(G.y, poy, piy, dy, ey, sp2);
-      split_fold(G.z, poz, piz, dz, ez, sp2);
-      // the best distance in the patch frame: best_t - pt0 carries the rounding of
-      // best_t = pt0 + t and of the difference (each at most 2^-24 relative), so it
-      // is widened by twice their bound and a leaf at the best distance is never pruned
-      const float cap = (best_t - pt0) + (fabsf(best_t) + fabsf(pt0)) * 0x1p-22f;
-      const float fa = fminf(widen_far(sp2.fa), cap), fb = fminf(widen_far(sp2.fb), cap);
-      const bool ha = sp2.na <= fa, hb = sp2.nb <= fb;
-      const float ta = sp2.na, tb = sp2.nb;
-      const int axis = depth & 1;
-      const bool mir = ((mirror >> axis) & 1u) != 0;
-      const bool h_lo = mir ? hb : ha, h_up = mir ? ha : hb;
-      const float t_lo = mir ? tb : ta, t_up = mir ? ta : tb;
-      bool go_up = h_up && (!h_lo || t_up < t_lo);
-      const uint32_t bit = 1u << (L2 - 1 - depth);
-      const uint32_t mirror0 = mirror;
-      bool decide = false;
-      if (kLearned) {
-        // v-split after a decision: the network's v-half when both are hit (not at the
-        // leaf pair, which is resolved by distance)
-        if ((vpref & 1u) && axis == 1 && ha && hb && depth != L2 - 1) go_up = (vpref & 2u) != 0;
-        vpref = 0;
-        decide = axis == 0 && ha && hb;
-      }
-      // the chosen half replaces the grid on every path: when the lane backtracks or
-      // leaves the patch instead, the grid is rebuilt before it is read again
-      const bool second = go_up != mir;
-      if (kLearned && decide) {
-        // the node's corners in storage order (0,0), (3,0), (0,3), (3,3) and its slab
-        // results, kept for the decision (formed there, off this phase's registers)
-        const float sx[4] = {ex[0].v[0], ex[0].v[6], ex[3].v[0], ex[3].v[6]};
-        const float sy[4] = {ey[0].v[0], ey[0].v[6], ey[3].v[0], ey[3].v[6]};
-        const float sz[4] = {ez[0].v[0], ez[0].v[6], ez[3].v[0], ez[3].v[6]};
-        policy_store_node(s_feat, lane, sx, sy, sz, sp2);
-        s_mirror[lane] = (uint8_t)mirror0;
-      }
-      take_half(ex, second, G.x);
-      take_half(ey, second, G.y);
-      take_half(ez, second, G.z);
-      bool backtrack = !(ha || hb);
-      if (!backtrack) {
-        if (depth == L2 - 1) {
-          const float tf = pt0 + (go_up ? t_up : t_lo);
+      bool backtrack;
+      if constexpr (kSingle) {
+        // the box of the current domain only: its grid's hull, the maximum side grown
+        // by the domain's own displacement
+        SlabPair one = {ptmin, __builtin_inff(), ptmin, __builtin_inff()};
+        grid_fold(G.x, pox, pix, dx, one);
+        grid_fold(G.y, poy, piy, dy, one);
+        grid_fold(G.z, poz, piz, dz, one);
+        const float cap = (best_t - pt0) + (fabsf(best_t) + fabsf(pt0)) * 0x1p-22f;
+        const bool hit = one.na <= fminf(widen_far(one.fa), cap);
+        backtrack = true;
+        if (hit && depth == L2) {
+          const float tf = pt0 + one.na;
           const uint32_t pid = pmeta & kIdMask;
           if (tf < best_t || (tf == best_t && pid < best_id)) {
-            const uint32_t lc = code | (go_up ? bit : 0u);
             best_t = tf;
             best_id = pid;
-            s_uv[0][lane] = (float)(2u * compact_even(lc >> 1) + 1u) * (0.5f * leaf_scale);
-            s_uv[1][lane] = (float)(2u * compact_even(lc) + 1u) * (0.5f * leaf_scale);
+            s_uv[0][lane] = (float)(2u * compact_even(code >> 1) + 1u) * (0.5f * leaf_scale);
+            s_uv[1][lane] = (float)(2u * compact_even(code) + 1u) * (0.5f * leaf_scale);
             if (kStats) cnt.leaf++;
           }
-          backtrack = true;
-        } else {
-          if (ha && hb) trail |= bit;
-          if (go_up) code |= bit;
+        } else if (hit) {
+          // split and enter the lower half, the upper one pending
+          const int axis = depth & 1;
+          const bool second = ((mirror >> axis) & 1u) != 0;  // the lower half is register-second when mirrored
+          Row7 ex[4], ey[4], ez[4];
+          SlabPair unused = {0.0f, 0.0f, 0.0f, 0.0f};
+          split_fold(G.x, 0.0f, 1.0f, 0.0f, ex, unused);
+          split_fold(G.y, 0.0f, 1.0f, 0.0f, ey, unused);
+          split_fold(G.z, 0.0f, 1.0f, 0.0f, ez, unused);
+          take_half(ex, second, G.x);
+          take_half(ey, second, G.y);
+          take_half(ez, second, G.z);
+          trail |= 1u << (L2 - 1 - depth);
           if (second) mirror ^= (1u << axis);
           depth++;
-          if (pmeta & kGregoryBit) mode = kGrid;  // Alg. 3 recomputes a Gregory grid at every node
-          if (kLearned && decide) mode = kDecide;
+          backtrack = false;
+          if (pmeta & kGregoryBit) mode = kGrid;  // the child's own bound (Alg. 2 on its domain)
+        }
+      } else {
+        // split each component and fold its two child boxes into the slab test at once
+        Row7 ex[4], ey[4], ez[4];
+        SlabPair sp2 = {ptmin, __builtin_inff(), ptmin, __builtin_inff()};
+        split_fold(G.x, pox, pix, dx, ex, sp2);
+        split_fold(G.y, poy, piy, dy, ey, sp2);
+        split_fold(G.z, poz, piz, dz, ez, sp2);
+        // the best distance in the patch frame: best_t - pt0 carries the rounding of
+        // best_t = pt0 + t and of the difference (each at most 2^-24 relative), so it
+        // is widened by twice their bound and a leaf at the best distance is never pruned
+        const float cap = (best_t - pt0) + (fabsf(best_t) + fabsf(pt0)) * 0x1p-22f;
+        const float fa = fminf(widen_far(sp2.fa), cap), fb = fminf(widen_far(sp2.fb), cap);
+        const bool ha = sp2.na <= fa, hb = sp2.nb <= fb;
+        const float ta = sp2.na, tb = sp2.nb;
+        const int axis = depth & 1;
+        const bool mir = ((mirror >> axis) & 1u) != 0;
+        const bool h_lo = mir ? hb : ha, h_up = mir ? ha : hb;
+        const float t_lo = mir ? tb : ta, t_up = mir ? ta : tb;
+        bool go_up = h_up && (!h_lo || t_up < t_lo);
+        const uint32_t bit = 1u << (L2 - 1 - depth);
+        const uint32_t mirror0 = mirror;
+        bool decide = false;
+        if (kLearned) {
+          // v-split after a decision: the network's v-half when both are hit (not at the
+          // leaf pair, which is resolved by distance)
+          if ((vpref & 1u) && axis == 1 && ha && hb && depth != L2 - 1) go_up = (vpref & 2u) != 0;
+          vpref = 0;
+          decide = axis == 0 && ha && hb;
+        }
+        // the chosen half replaces the grid on every path: when the lane backtracks or
+        // leaves the patch instead, the grid is rebuilt before it is read again
+        const bool second = go_up != mir;
+        if (kLearned && decide) {
+          // the node's corners in storage order (0,0), (3,0), (0,3), (3,3) and its slab
+          // results, kept for the decision (formed there, off this phase's registers)
+          const float sx[4] = {ex[0].v[0], ex[0].v[6], ex[3].v[0], ex[3].v[6]};
+          const float sy[4] = {ey[0].v[0], ey[0].v[6], ey[3].v[0], ey[3].v[6]};
+          const float sz[4] = {ez[0].v[0], ez[0].v[6], ez[3].v[0], ez[3].v[6]};
+          policy_store_node(s_feat, lane, sx, sy, sz, sp2);
+          s_mirror[lane] = (uint8_t)mirror0;
+        }
+        take_half(ex, second, G.x);
+        take_half(ey, second, G.y);
+        take_half(ez, second, G.z);
+        backtrack = !(ha || hb);
+        if (!backtrack) {
+          if (depth == L2 - 1) {
+            const float tf = pt0 + (go_up ? t_up : t_lo);
+            const uint32_t pid = pmeta & kIdMask;
+            if (tf < best_t || (tf == best_t && pid < best_id)) {
+              const uint32_t lc = code | (go_up ? bit : 0u);
+              best_t = tf;
+              best_id = pid;
+              s_uv[0][lane] = (float)(2u * compact_even(lc >> 1) + 1u) * (0.5f * leaf_scale);
+              s_uv[1][lane] = (float)(2u * compact_even(lc) + 1u) * (0.5f * leaf_scale);
+              if (kStats) cnt.leaf++;
+            }
+            backtrack = true;
+          } else {
+            if (ha && hb) trail |= bit;
+            if (go_up) code |= bit;
+            if (second) mirror ^= (1u << axis);
+            depth++;
+            if (pmeta & kGregoryBit) mode = kGrid;  // Alg. 3 recomputes a Gregory grid at every node
+            if (kLearned && decide) mode = kDecide;
+          }
         }
       }
       if (backtrack) {
@@ -470,22 +518,132 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   }
 }
 
+template <bool kStats, bool kLearned>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
+                                                  LaunchParams lp) {
+  trace_body<kStats, kLearned, false>(s, bt, counters, lp);
+}
+
+template <bool kStats>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_single_box(
+    DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters, LaunchParams lp) {
+  trace_body<kStats, false, true>(s, bt, counters, lp);
+}
+
+// Grid of a subdomain by both of the kernel's routes, for measuring their fp32
+// deviation (Sec. 3.4 compares recomputed control points with subdivided ones).
+// One thread per query q = (patch record, path code, depth), with the path code
+// laid out as in k_trace.  Output row of kDebugGridFloats floats:
+//   [0, 60)    the record's stored points: x, y, z of slots 0..15, then x, y, z of P^v
+//   [60, 108)  calcPointsAndD on the domain, as the grid phase computes it (one
+//              component at a time): x, y, z of q[i][j] at 16 c + 4 j + i
+//   [108, 111) its displacement d
+//   [111, 159) Bezier patches: the root grid split depth times along the path by
+//              the split step's arithmetic (de Casteljau halves, transposed and
+//              mirrored write-back), un-oriented to the same layout; NaN for Gregory
+//   [159]      0 for a valid query, NaN when the query is out of range
+template <int kF>
+__device__ __forceinline__ void store_canonical(float* out, const float g[4][4], bool odd, uint32_t mirror, int c) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      // register (a, b): a runs along the next split's axis (u at even depth)
+      const int ra = odd ? b : a, rb = odd ? a : b;  // register indices along u, along v
+      const int i = (mirror & 1u) ? 3 - ra : ra, j = (mirror & 2u) ? 3 - rb : rb;
+      out[kF + 16 * c + 4 * j + i] = g[a][b];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_debug_grids(DeviceScene s, const uint32_t* __restrict__ patch,
+                                                    const uint32_t* __restrict__ code_in,
+                                                    const uint32_t* __restrict__ depth_in, uint32_t n,
+                                                    float* __restrict__ out) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  float* o = out + (size_t)q * kDebugGridFloats;
+  const uint32_t pid = patch[q], code = code_in[q], depth = depth_in[q];
+  const int L2 = 2 * s.leaf_depth;
+  // the path code holds bits for the depth splits taken and none below or above them
+  const bool valid = pid < s.n_patches && depth <= (uint32_t)L2 &&
+                     ((uint64_t)code & ((1ull << (L2 - (int)depth)) - 1ull)) == 0 && ((uint64_t)code >> L2) == 0;
+  if (!valid) {
+    for (int k = 0; k < kDebugGridFloats; ++k) o[k] = __uint_as_float(0x7FC00000u);
+    return;
+  }
+  const float* rec = s.recs + (size_t)s.inv_perm[pid] * kRecFloats;
+  for (int k = 0; k < 60; ++k) o[k] = rec[k];
+  const bool greg = (__float_as_uint(rec[63]) & kGregoryBit) != 0;
+  const float leaf_scale = __uint_as_float((uint32_t)(127 - s.leaf_depth) << 23);
+  const float u0 = (float)compact_even(code >> 1) * leaf_scale, v0 = (float)compact_even(code) * leaf_scale;
+  const float su = __uint_as_float((uint32_t)(127 - (((int)depth + 1) >> 1)) << 23);
+  const float sv = __uint_as_float((uint32_t)(127 - ((int)depth >> 1)) << 23);
+  for (int c = 0; c < 3; ++c) {
+    float qc[4][4], dc;
+    calc_component(rec + 16 * c, rec + 48 + 4 * c, greg, u0, u0 + su, v0, v0 + sv, qc, dc);
+    store_canonical<60>(o, qc, false, 0u, c);
+    o[108 + c] = dc;
+  }
+  if (greg) {
+    for (int k = 111; k < 159; ++k) o[k] = __uint_as_float(0x7FC00000u);
+  } else {
+    PatchPts P;
+    load_grid(rec, P, false);
+    Grid G;
+    orient(P.x, false, G.x);
+    orient(P.y, false, G.y);
+    orient(P.z, false, G.z);
+    uint32_t mirror = 0;
+    for (uint32_t k = 0; k < depth; ++k) {
+      const int axis = (int)(k & 1u);
+      const bool up = (code >> (L2 - 1 - (int)k)) & 1u;
+      const bool mir = ((mirror >> axis) & 1u) != 0;
+      Row7 ex[4], ey[4], ez[4];
+      SlabPair sp2 = {0.0f, 0.0f, 0.0f, 0.0f};  // the slab results are not used here
+      split_fold(G.x, 0.0f, 1.0f, 0.0f, ex, sp2);
+      split_fold(G.y, 0.0f, 1.0f, 0.0f, ey, sp2);
+      split_fold(G.z, 0.0f, 1.0f, 0.0f, ez, sp2);
+      const bool second = up != mir;
+      take_half(ex, second, G.x);
+      take_half(ey, second, G.y);
+      take_half(ez, second, G.z);
+      if (second) mirror ^= 1u << axis;
+    }
+    const bool odd = (depth & 1u) != 0;
+    store_canonical<111>(o, G.x, odd, mirror, 0);
+    store_canonical<111>(o, G.y, odd, mirror, 1);
+    store_canonical<111>(o, G.z, odd, mirror, 2);
+  }
+  o[159] = 0.0f;
+}
+
+hipError_t launch_debug_grids(const DeviceScene& s, const uint32_t* patch, const uint32_t* code,
+                              const uint32_t* depth, uint32_t n, float* out, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug_grids, dim3((n + 63) / 64), dim3(64), 0, stream, s, patch, code, depth, n, out);
+  return hipGetLastError();
+}
+
 __global__ void k_queue_reset(uint32_t* q) { *q = 0u; }
 
-template <bool kStats, bool kLearned>
+template <bool kStats, bool kLearned, bool kSingle>
 static int resident_waves_per_cu() {
   static int per_cu = -1;
   if (per_cu < 0) {
     int v = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace<kStats, kLearned>, kBlock, 0);
+    if (kSingle)
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace_single_box<kStats>, kBlock, 0);
+    else
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace<kStats, kLearned>, kBlock, 0);
     per_cu = std::max(1, v);
   }
   return per_cu;
 }
 
-int max_waves_per_cu(bool counted, bool learned) {
-  if (learned) return counted ? resident_waves_per_cu<true, true>() : resident_waves_per_cu<false, true>();
-  return counted ? resident_waves_per_cu<true, false>() : resident_waves_per_cu<false, false>();
+int max_waves_per_cu(bool counted, bool learned, bool single_box) {
+  if (single_box) return counted ? resident_waves_per_cu<true, false, true>() : resident_waves_per_cu<false, false, true>();
+  if (learned) return counted ? resident_waves_per_cu<true, true, false>() : resident_waves_per_cu<false, true, false>();
+  return counted ? resident_waves_per_cu<true, false, false>() : resident_waves_per_cu<false, false, false>();
 }
 
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
@@ -493,13 +651,18 @@ hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t
   const uint32_t n = bt.prefix[bt.n_batches];
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, stream, lp.queue);
-  const bool learned = s.policy.w != nullptr;
-  int per_cu = max_waves_per_cu(counters != nullptr, learned);
+  const bool learned = s.policy.w != nullptr && !s.single_box;
+  int per_cu = max_waves_per_cu(counters != nullptr, learned, s.single_box);
   if (waves_per_cu > 0) per_cu = std::min(per_cu, (int)waves_per_cu);
   const uint32_t waves = (uint32_t)(per_cu * s.n_cus);
   const uint32_t needed = (n + kBlock - 1) / kBlock;
   const dim3 grid(std::min(waves, needed)), block(kBlock);
-  if (learned) {
+  if (s.single_box) {
+    if (counters)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_single_box<true>), grid, block, 0, stream, s, bt, counters, lp);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_single_box<false>), grid, block, 0, stream, s, bt, nullptr, lp);
+  } else if (learned) {
     if (counters)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace<true, true>), grid, block, 0, stream, s, bt, counters, lp);
     else

@@ -257,7 +257,8 @@ def surface_bounce_rays(cp: np.ndarray, types: np.ndarray, leaf_depth: int, eye,
     out = np.zeros((n, 8), dtype=np.float32)
     eye = np.asarray(eye, dtype=np.float64)
     h = 1e-6
-    for b in range(0, n, chunk):
+
+    def one_chunk(b):  # chunks are independent: their uniforms are drawn above
         e = min(n, b + chunk)
         idx, u, v = idx_all[b:e], u_all[b:e], v_all[b:e]
         g, greg = _blended_grids(cp, types, idx)
@@ -273,6 +274,15 @@ def surface_bounce_rays(cp: np.ndarray, types: np.ndarray, leaf_depth: int, eye,
         d /= np.linalg.norm(d, axis=-1, keepdims=True)
         out[b:e, 0:3] = o
         out[b:e, 4:7] = d
+
+    starts = range(0, n, chunk)
+    if len(starts) > 4:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(one_chunk, starts))
+    else:
+        for b in starts:
+            one_chunk(b)
     out[:, 7] = np.inf
     return out
 

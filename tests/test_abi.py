@@ -68,7 +68,7 @@ def test_host_validation_errors():
         c2[2, 7, 1] = v
         st, msg, _ = create(host_desc(c2, ty))
         assert st == ccs.CCS_ERR_INVALID_ARG and "finite" in msg
-    for flags in (2, 0x80000000):  # bit 0 (local frames) is the only flag
+    for flags in (4, 0x80000000):  # bits 0 (local frames) and 1 (single-box ablation) are the only flags
         st, msg, _ = create(host_desc(cp, ty, flags=flags))
         assert st == ccs.CCS_ERR_UNSUPPORTED and "flags" in msg
     st, msg, _ = create(host_desc(cp, ty, location=7))

@@ -263,3 +263,54 @@ def test_combined_pipeline_with_learned_order(anim, scene):
             _say(f"combined: level {b}, frame {f}: {len(r)} rays")
             assert_gate(gate(h, osc.intersect(r), r, osc, anim.diameter, anim.leaf_depth,
                              label=f"combined-level{b}-frame{f}"))
+
+
+def test_combined_pipeline_at_one_million_patches():
+    """The combined pipeline at the 1M-patch scale: two animation frames of the
+    1M-patch scene (the seeded displacement), each refit on the GPU, the 1920x1080
+    primary rays of both frames in one batched launch, then one bounce level
+    generated per frame from those hits and intersected in one batched launch with
+    the learned order on (an untrained network: the order never decides a hit).
+    Each (frame, level) passes the oracle gate on 32,768 seeded rays of that frame's
+    geometry, and the counted batched launch gives bitwise the same hits."""
+    from paper_1811_03510_amd import ccs
+    w = S.config2(with_diffuse=False)
+    F = 2
+    frames = [S.animate(w.cp, f, 8) for f in (0, 5)]
+    _say("1M combined: building the scene and two frames")
+    sc = ccs.Scene(torch.from_numpy(w.cp).cuda(), torch.from_numpy(w.types).cuda(), w.leaf_depth, local_frames=True)
+    sc.set_frames(F)
+    cps = [torch.from_numpy(c).cuda() for c in frames]
+    for f in range(F):
+        sc.refit_frame(f, cps[f])
+    prim = torch.from_numpy(w.primary).cuda()
+    h0 = sc.intersect_batched([(f, prim, None) for f in range(F)])
+    rng = np.random.default_rng(41)
+    brays = []
+    for f in range(F):
+        u = torch.from_numpy(rng.uniform(size=(prim.shape[0], 2)).astype(np.float32)).cuda()
+        brays.append(sc.bounce(prim, h0[f], u, frame=f))
+    theta = torch.from_numpy((rng.normal(size=ccs.POLICY_PARAMS) * 0.5).astype(np.float32)).cuda()
+    sc.set_policy(theta)
+    try:
+        _say("1M combined: bounce level, learned order")
+        h1 = sc.intersect_batched([(f, brays[f], None) for f in range(F)])
+        torch.cuda.synchronize()
+    finally:
+        sc.set_policy(None)
+    hc, _ = sc.intersect_batched([(f, prim, None) for f in range(F)], counted=True)
+    torch.cuda.synchronize()
+    for f in range(F):
+        assert np.array_equal(hc[f].cpu().numpy().view(np.uint32), h0[f].cpu().numpy().view(np.uint32))
+    for f in range(F):
+        osc = O.Scene(frames[f], w.types, w.leaf_depth, local_frames=True)
+        for lvl, (r, h) in enumerate(((prim, h0[f]), (brays[f], h1[f]))):
+            r_np, h_np = r.cpu().numpy(), h.cpu().numpy()
+            active = np.flatnonzero(r_np[:, 3] <= r_np[:, 7])  # rays of missed pixels are inactive
+            sel = active[S.sample_indices(len(active), min(32768, len(active)), seed=300 + 10 * f + lvl)]
+            _say(f"1M combined: frame {f}, level {lvl}: gate on {len(sel)} of {len(active)} active rays")
+            rep = gate(h_np[sel], osc.intersect(r_np[sel]), r_np[sel], osc, w.diameter, w.leaf_depth,
+                       label=f"1M-combined-frame{f}-level{lvl}")
+            assert_gate(rep)
+            assert rep["oracle_hits"] > 1000
+        del osc

@@ -206,3 +206,39 @@ def test_far_hit_behind_a_thin_leaf_box_is_hard(c1):
         g[hit, 2], g[hit, 3] = 0.5 * 2.0 ** -c1.leaf_depth, 0.5
         rep = gate(g, o, rays, osc, c1.diameter, c1.leaf_depth)
         assert rep["excused"]["hard"] == len(hit), (local, rep["excused"])
+
+
+def test_ray_starting_within_rounding_of_a_leaf_box(c1):
+    """A GPU hit at tmin on a leaf box the ray starts just outside of (by a quarter of
+    the slack, so only rounding put the start inside) is a graze; the same report
+    with the start four slacks outside, or with a later distance, is hard."""
+    L = c1.leaf_depth
+    checked = 0
+    for local in (False, True):
+        osc = O.Scene(c1.cp, c1.types, L, local_frames=local)
+        rng = np.random.default_rng(17)
+        for pid in rng.choice(len(c1.cp), 12, replace=False):
+            uc, vc = (rng.integers(0, 2 ** L) + 0.5) * 2.0 ** -L, (rng.integers(0, 2 ** L) + 0.5) * 2.0 ** -L
+            lo, hi = osc.leaf_box(pid, uc, vc)
+            slack = 1e-3 * np.linalg.norm(hi - lo) + 1e-7
+            R = osc.patch_frame(int(pid))
+            kinds = []
+            for gap, t_rep in ((0.25 * slack, 0.0), (4.0 * slack, 0.0), (0.25 * slack, 1e-3 * c1.diameter)):
+                # start beyond the box's largest face along frame axis 2, moving away from it
+                pf = 0.5 * (lo + hi)
+                pf[2] = hi[2] + gap
+                df = np.array([0.3, -0.2, 1.0])
+                df /= np.linalg.norm(df)
+                ray = np.array([*(R.T @ pf), 0.0, *(R.T @ df), np.inf])
+                o = osc.intersect_f64(ray[None])  # the ray in double: the planted gap is exact
+                g = np.zeros((1, 4), np.float32)
+                g[0, 0] = t_rep
+                g[0, 1] = np.array([pid], np.uint32).view(np.float32)[0]
+                g[0, 2], g[0, 3] = uc, vc
+                rep = gate(g, o, ray[None], osc, c1.diameter, L)
+                kinds.append([k for k, v in rep["excused"].items() if v])
+            if kinds[0] == []:
+                continue  # the oracle reports this leaf itself (the float ray starts inside it)
+            assert kinds == [["graze"], ["hard"], ["hard"]], (local, pid, kinds)
+            checked += 1
+    assert checked >= 10
