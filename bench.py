@@ -493,8 +493,13 @@ def main():
             variants["batched_bounce"]["parity_sample"] = {"bounce": summary(rb), "primary": summary(rbp)}
             gates["batched_bounce"] = rb["ok"] and rbp["ok"]
         if single_hits is not None:
-            sp_ = gate(single_hits[0][sel_p], op, w.primary[sel_p], osc, w.diameter, w.leaf_depth, label="1box-primary")
-            sd_ = gate(single_hits[1][sel_d], od, w.diffuse[sel_d], osc, w.diameter, w.leaf_depth, label="1box-diffuse")
+            # against the oracle's own single-box mode (a Gregory leaf tested by its own bound)
+            ss_p = scenes.sample_indices(n_p, min(n_p, 65536), seed=97)
+            ss_d = scenes.sample_indices(n_d, min(n_d, 65536), seed=98)
+            osp = osc.intersect_single_box(w.primary[ss_p], nthreads=threads)
+            osd = osc.intersect_single_box(w.diffuse[ss_d], nthreads=threads)
+            sp_ = gate(single_hits[0][ss_p], osp, w.primary[ss_p], osc, w.diameter, w.leaf_depth, label="1box-primary")
+            sd_ = gate(single_hits[1][ss_d], osd, w.diffuse[ss_d], osc, w.diameter, w.leaf_depth, label="1box-diffuse")
             variants["batched_single_box"]["parity_sample"] = {"primary": summary(sp_), "diffuse": summary(sd_)}
             gates["batched_single_box"] = sp_["ok"] and sd_["ok"]
         if learned_hits is not None:

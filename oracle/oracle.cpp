@@ -345,7 +345,12 @@ struct Split {
 //   kLookahead: on every patch, the half whose first visit costs fewer split steps
 //               over the node's subtree (both orders tried, closest-first below):
 //               the order a perfect predictor of that work label gives.
-enum OrderMode { kHindsight = 0, kLookahead = 1 };
+//   kSingleBox: not an order but the alternative Sec. 3.3 measures its two-box test
+//               against: every node tests only its own box (its grid bounded on its
+//               own domain by Alg. 2, with its own displacement); a hit node above
+//               the leaf depth has both halves visited, the lower one first, and a
+//               hit leaf is recorded at its own entry distance.
+enum OrderMode { kHindsight = 0, kLookahead = 1, kSingleBox = 2 };
 struct OrderHint {
   int mode;
   uint32_t id, pu, pv;
@@ -402,8 +407,47 @@ static void push_children(const Patch& P, const Frame& f, const Grid& gl, const 
   stack.push_back(ch[0]);
 }
 
+static void intersect_patch_single_box(const Patch& P, uint32_t id, const Ray& r, int L, Best& best,
+                                       Counters& c) {
+  struct Dom {
+    uint32_t pu, pv, su, sv;
+    int depth;
+  };
+  std::vector<Dom> stack;
+  stack.reserve(2 * L + 2);
+  stack.push_back({0, 0, kFull, kFull, 0});
+  while (!stack.empty()) {
+    const Dom f = stack.back();
+    stack.pop_back();
+    const Bound b = calc_points_and_d_int(P, f.pu, f.pv, f.su, f.sv);  // a Bezier patch: its crop, d = 0
+    c.split++;
+    V3 lo, hi;
+    grid_box(b.q, b.d, P.pad, &lo, &hi);
+    double t = 0.0;
+    if (!slab(r, lo, hi, best.t, &t)) continue;
+    if (f.depth == 2 * L) {
+      if (better(t, id, best)) {
+        best.t = t;
+        best.id = id;
+        best.u = (f.pu + f.su / 2) * kUnit;
+        best.v = (f.pv + f.sv / 2) * kUnit;
+        c.leaf++;
+      }
+      continue;
+    }
+    const int axis = f.depth & 1;
+    const uint32_t csu = axis == 0 ? f.su / 2 : f.su, csv = axis == 1 ? f.sv / 2 : f.sv;
+    stack.push_back({axis == 0 ? f.pu + csu : f.pu, axis == 1 ? f.pv + csv : f.pv, csu, csv, f.depth + 1});
+    stack.push_back({f.pu, f.pv, csu, csv, f.depth + 1});  // the lower half first
+  }
+}
+
 static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Best& best,
                             Counters& c, std::vector<Split>* trace, const OrderHint* hint = nullptr) {
+  if (hint && hint->mode == kSingleBox) {
+    intersect_patch_single_box(P, id, r, L, best, c);
+    return;
+  }
   std::vector<Frame> stack;
   stack.reserve(4 * L + 4);  // at most one pending sibling per level
   Frame root;
@@ -988,7 +1032,7 @@ void orc_intersect_hinted(void* s, const float* rays, uint32_t n, int nthreads, 
     h.id = hint_id[i];
     h.pu = std::min((uint32_t)(hint_u[i] / kUnit) & ~(leaf - 1), kFull - leaf);
     h.pv = std::min((uint32_t)(hint_v[i] / kUnit) & ~(leaf - 1), kFull - leaf);
-    trace_ray(S, r, b, c, (mode == kHindsight && h.id == kNoHit) ? nullptr : &h);
+    trace_ray(S, r, b, c, (mode == kHindsight && h.id == kNoHit) ? nullptr : &h);  // kSingleBox ignores the hint
     t[i] = b.t;
     id[i] = b.id;
     u[i] = b.u;

@@ -1,8 +1,10 @@
 """The one-box-per-step ablation (CCS_FLAG_SINGLE_BOX; Sec. 3.3 reports that testing
-the two child boxes instead nearly halves traversal time).  It must give the
-oracle's hits under the same gate, and it must do more subdivision work per ray:
-without the child boxes' distances no half can be pruned before its grid exists,
-and every pending half costs a recompute."""
+the two child boxes instead nearly halves traversal time).  It must give the hits of
+the oracle's single-box mode under the same gate (a Gregory leaf is then tested by
+its own bound, not by the half of its parent's grid that Alg. 3 tests, so a ray
+grazing the difference may name a neighbouring leaf), and it must do more
+subdivision work per ray: without the child boxes' distances no half can be pruned
+before its grid exists, and every pending half costs a recompute."""
 import numpy as np
 import pytest
 
@@ -32,7 +34,7 @@ def test_single_box_matches_oracle_and_does_more_work(c1, local):
         h2, c_two = two.intersect_counted(r)
         torch.cuda.synchronize()
         g = h1.cpu().numpy()
-        assert_gate(gate(g, osc.intersect(rays), rays, osc, c1.diameter, L, label=f"single-box-{cls}"))
+        assert_gate(gate(g, osc.intersect_single_box(rays), rays, osc, c1.diameter, L, label=f"single-box-{cls}"))
         # the plain launch gives the counted launch's hits
         assert np.array_equal(one.intersect(r).cpu().numpy().view(np.uint32), g.view(np.uint32))
         c_one, c_two = c_one.cpu().numpy().astype(np.float64), c_two.cpu().numpy().astype(np.float64)

@@ -46,3 +46,30 @@ def test_hindsight_hint_steers_the_order(c1, c1_oracle):
     h = c1_oracle.intersect_hinted(rays, wrong)
     assert np.array_equal(h["id"], o["id"]) and np.allclose(h["t"][hit], o["t"][hit], rtol=1e-12, atol=0)
     assert h["counters"][:, 2].sum() > o["counters"][:, 2].sum()
+
+
+def test_single_box_mode_equals_alg3_on_bezier_patches(c1):
+    """The oracle's single-box mode (Sec. 3.3's alternative: each node tests only its
+    own box, the crop of the grid to its domain) against Alg. 3's two-box recursion
+    (child boxes from de Casteljau halves): on Bezier patches a child's box is the
+    same box either way and the closest leaf is reached by both, so every hit is
+    the same leaf at the same distance (up to the crop's rounding); and the mode
+    takes more box tests per ray, as Sec. 3.3 reports.  With Gregory patches the
+    leaf boxes differ (own bound vs the parent's half), so hits may move to a
+    neighbouring leaf within the distance tolerance."""
+    types0 = np.zeros_like(c1.types)
+    for local in (False, True):
+        osc = O.Scene(c1.cp, types0, c1.leaf_depth, local_frames=local)
+        for rays in (c1.primary, c1.diffuse):
+            a = osc.intersect(rays, counters=True)
+            b = osc.intersect_single_box(rays)
+            hit = a["id"] != O.NO_HIT
+            assert np.array_equal(a["id"], b["id"])
+            assert np.allclose(a["t"][hit], b["t"][hit], rtol=1e-12, atol=1e-13)
+            assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["v"], b["v"])
+            assert b["counters"][:, 2].mean() > 1.5 * a["counters"][:, 2].mean()
+    osc = O.Scene(c1.cp, c1.types, c1.leaf_depth)
+    a, b = osc.intersect(c1.diffuse), osc.intersect_single_box(c1.diffuse)
+    hit = a["id"] != O.NO_HIT
+    assert np.array_equal(a["id"], b["id"])
+    assert np.abs(a["t"][hit] - b["t"][hit]).max() <= 1e-4 * c1.diameter
