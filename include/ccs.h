@@ -313,6 +313,19 @@ ccs_status ccs_policy_infer(const float* params, const float* features, uint32_t
 ccs_status ccs_policy_grad(const float* params, const float* features, const uint8_t* labels, uint32_t n,
                            uint32_t bf16, float* grad, float* loss, void* stream);
 
+/* ccs_policy_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * allocation): the same kernels and results, with the per-block partial
+ * gradients in a preallocated device array of the library (1.7 MiB per device,
+ * held until the process ends) instead of temporaries.  Asynchronous on `stream`
+ * (no synchronization).  At most 16384 rows (CCS_ERR_INVALID_ARG beyond).
+ * Every call on one device shares that array: calls that overlap on a device
+ * (other streams, other threads) race and must be serialized by the caller; a
+ * call's grad and loss are final once its stream has passed it. */
+#define CCS_GRAD_NOALLOC_MAX_ROWS 16384
+ccs_status ccs_policy_grad_noalloc(const float* params, const float* features, const uint8_t* labels, uint32_t n,
+                                   uint32_t bf16, float* grad, float* loss, void* stream);
+
 typedef struct ccs_train_params {
   uint32_t steps;  /* optimizer steps */
   uint32_t batch;  /* rows per step (at most n); an epoch is floor(n / batch) steps */

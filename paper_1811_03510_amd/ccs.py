@@ -27,13 +27,14 @@ EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_coun
            "ccs_scene_info_get", "ccs_scene_destroy", "ccs_last_error", "ccs_scene_set_launch",
            "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched",
            "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train",
-           "ccs_bounce_frame", "ccs_device_bytes_in_use", "ccs_debug_grids",
+           "ccs_bounce_frame", "ccs_device_bytes_in_use", "ccs_debug_grids", "ccs_policy_grad_noalloc",
            "ccs_intersect_batched_counted")
 MAX_BATCHES = 32
 MAX_RAYS = (1 << 31) - 1  # per call
 POLICY_PARAMS = 1732
 NO_LABEL = 255
 DEBUG_GRID_FLOATS = 160
+GRAD_NOALLOC_MAX_ROWS = 16384
 
 
 class CcsError(RuntimeError):
@@ -105,6 +106,7 @@ def lib():
         L.ccs_policy_record.argtypes = [vp, vp, vp, u32, vp, vp, vp]
         L.ccs_policy_infer.argtypes = [vp, vp, u32, vp, vp]
         L.ccs_policy_grad.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
+        L.ccs_policy_grad_noalloc.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
         L.ccs_policy_train.argtypes = [vp, vp, vp, u32, C.POINTER(TrainParams), C.POINTER(AdamState), vp, vp]
         L.ccs_debug_grids.argtypes = [vp, u32, vp, vp, vp, u32, vp, vp]
         L.ccs_device_bytes_in_use.argtypes = []
@@ -371,6 +373,25 @@ def policy_grad(params, features, labels, bf16: bool = False, stream=None):
     _check(lib().ccs_policy_grad(_ptr(p), _ptr(f), _ptr(y), f.shape[0], int(bf16), _ptr(g), _ptr(loss),
                                  _stream(stream)))
     return float(loss.item()), g
+
+
+def policy_grad_noalloc(params, features, labels, grad, loss, bf16: bool = False, stream=None):
+    """policy_grad into caller-given grad (1732,) and loss (1,) float32 CUDA tensors,
+    with the library's preallocated scratch (no device allocation; asynchronous;
+    at most GRAD_NOALLOC_MAX_ROWS rows; calls overlapping on one device race)."""
+    import torch
+    p, f = _params(params), _rows(features, 16, torch.float32)
+    y = _rows(labels, 0, torch.uint8)
+    if y.numel() != f.shape[0]:
+        raise ValueError("one label per row")
+    for t, k, name in ((grad, POLICY_PARAMS, "grad"), (loss, 1, "loss")):
+        if not (torch.is_tensor(t) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and t.numel() == k):
+            raise ValueError(f"{name} must be a contiguous CUDA float32 tensor of {k} values")
+    if f.shape[0] > GRAD_NOALLOC_MAX_ROWS:
+        raise ValueError(f"at most {GRAD_NOALLOC_MAX_ROWS} rows")
+    _check(lib().ccs_policy_grad_noalloc(_ptr(p), _ptr(f), _ptr(y), f.shape[0], int(bf16), _ptr(grad), _ptr(loss),
+                                         _stream(stream)))
 
 
 class Adam:

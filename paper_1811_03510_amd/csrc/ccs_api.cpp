@@ -725,6 +725,31 @@ ccs_status ccs_policy_grad(const float* params, const float* features, const uin
   return CCS_OK;
 }
 
+ccs_status ccs_policy_grad_noalloc(const float* params, const float* features, const uint8_t* labels, uint32_t n,
+                                   uint32_t bf16, float* grad, float* loss, void* stream) {
+  g_error.clear();
+  if (!params || !grad || !loss || (n > 0 && (!features || !labels)))
+    return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if (n > ccs::kGradScratchBlocks * 64u)
+    return fail(CCS_ERR_INVALID_ARG, "n = " + std::to_string(n) + " rows exceeds the " +
+                                         std::to_string(ccs::kGradScratchBlocks * 64u) +
+                                         " rows of the preallocated gradient scratch");
+  float *partial = nullptr, *lossp = nullptr;
+  hipError_t e = ccs::grad_scratch(&partial, &lossp);
+  if (e != hipSuccess) return hip_fail(e, "gradient scratch address");
+  hipStream_t str = (hipStream_t)stream;
+  const uint32_t nblk = std::max<uint32_t>(1, (n + 63) / 64);
+  if (n == 0) {  // one block of zeros (a fill kernel, no memset node under graph capture)
+    e = ccs::launch_fill(partial, ccs::kPolicyParams, 0.0f, str);
+    if (e == hipSuccess) e = ccs::launch_fill(lossp, 2, 0.0f, str);
+  } else {  // every block writes its whole partial row and its loss pair
+    e = ccs::launch_mlp_grad(params, features, labels, n, n, 0, 1, 0, bf16 != 0, partial, lossp, str);
+  }
+  if (e == hipSuccess) e = ccs::launch_mlp_reduce(partial, lossp, nblk, grad, loss, str);
+  if (e != hipSuccess) return hip_fail(e, "policy gradient");
+  return CCS_OK;
+}
+
 ccs_status ccs_policy_train(float* params, const float* features, const uint8_t* labels, uint32_t n,
                             const ccs_train_params* tp, ccs_adam_state* state, float* loss_history, void* stream) {
   g_error.clear();

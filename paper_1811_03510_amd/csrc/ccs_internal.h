@@ -89,6 +89,10 @@ hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* partia
                            float lr, float beta1, float beta2, float eps, float c1, float c2, float* loss,
                            hipStream_t stream);
 hipError_t launch_fill(float* p, uint32_t n, float value, hipStream_t stream);
+// Rows of the gradient entry point that allocates nothing: at most
+// kGradScratchBlocks blocks of 64 (1.7 MiB of device scratch per device).
+constexpr uint32_t kGradScratchBlocks = 256;
+hipError_t grad_scratch(float** partial, float** lossp);
 constexpr int kDebugGridFloats = 160;
 hipError_t launch_debug_grids(const DeviceScene& s, const uint32_t* patch, const uint32_t* code,
                               const uint32_t* depth, uint32_t n, float* out, hipStream_t stream);

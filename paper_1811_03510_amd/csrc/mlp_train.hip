@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "policy.h"
 
 namespace ccs {
@@ -256,6 +258,32 @@ hipError_t launch_fill(float* p, uint32_t n, float value, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, value);
   return hipGetLastError();
+}
+
+// Gradient scratch of the entry point that allocates nothing: partial rows of
+// kGradScratchBlocks blocks, then their (loss, count) pairs.  One copy per device,
+// held until the process ends; every call on a device shares it.
+static __device__ __align__(256) float scratch[kGradScratchBlocks * (kPolicyParams + 2)];
+
+hipError_t grad_scratch(float** partial, float** lossp) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* base[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!base[dev]) {
+    // the array's address on the current device (its host-side name is not a device address)
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    base[dev] = static_cast<float*>(p);
+  }
+  *partial = base[dev];
+  *lossp = base[dev] + (size_t)kGradScratchBlocks * kPolicyParams;
+  return hipSuccess;
 }
 
 }  // namespace ccs
