@@ -814,11 +814,16 @@ def bench_combined(args, torch, ccs, scenes):
         torch.cuda.synchronize()
         ms = a.elapsed_time(z) / args.steps
         lvl = [float(np.median([e[b].elapsed_time(e[b + 1 + B]) for e in evs])) for b in range(B + 1)]
-        total = F * (B + 1) * n
+        # rays traced: every primary ray, and the bounce rays of pixels whose previous ray hit
+        # (the others are inactive, tmin > tmax, and are not counted); the same every step
+        live = [F * n] + [int(sum(int((rays[b][f][:, 3] <= rays[b][f][:, 7]).sum().item()) for f in range(F)))
+                          for b in range(1, B + 1)]
+        total = sum(live)
         active = [float((hits[b][0][:, 0] < float("inf")).float().mean().item()) for b in range(B + 1)]
         res = {"ms_per_step": ms, "mrays_per_s": total / (ms * 1e-3) / 1e6, "launch": scene.get_launch(),
+               "rays_per_step": total, "launched_rays_per_step": F * (B + 1) * n, "rays_per_level": live,
                "intersect_ms_per_level": lvl,
-               "mrays_per_s_per_level": [F * n / (t * 1e-3) / 1e6 for t in lvl],
+               "mrays_per_s_per_level": [k / (t * 1e-3) / 1e6 for k, t in zip(live, lvl)],
                "hit_fraction_frame0_per_level": active}
         log(f"{label}: {ms:.1f} ms/step -> {res['mrays_per_s']:.1f} MRays/s; levels {[round(t, 2) for t in lvl]} ms")
         return res
@@ -887,7 +892,9 @@ def bench_combined(args, torch, ccs, scenes):
         "warmup": args.warmup, "ms_per_step": round(variants[head]["ms_per_step"], 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
         "config": {"workload": f"{w.name}: {w.cp.shape[0]} patches, {F} frames, {n} primary rays + {B} bounces "
-                               f"per frame ({F * (B + 1) * n} rays per step)", "leaf_depth": w.leaf_depth,
+                               f"per frame ({variants[head]['rays_per_step']} active rays of "
+                               f"{F * (B + 1) * n} launched per step; a bounce of a missed ray is inactive)",
+                   "leaf_depth": w.leaf_depth,
                    "frames": "world" if args.world_frames else "patch-local (Sec. 3.4)",
                    "variant": "closest-first order, batched over frames"},
         "variants": variants, "roofline": variants[head].get("roofline"), "cpu_baseline": cpu, "parity_sample": parity,
