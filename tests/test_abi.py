@@ -138,3 +138,17 @@ def test_ray_count_bound_is_checked_before_any_launch():
         assert "2^31" in L.ccs_last_error().decode()
         assert L.ccs_intersect_counted(fake, fake, n, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
 
+
+
+def test_measurement_and_noalloc_entry_points_validate_on_the_host():
+    L = ccs.lib()
+    fake = C.c_void_p(16)  # never dereferenced: each call fails validation first
+    assert L.ccs_debug_grids(None, 0, fake, fake, fake, 4, fake, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_intersect_batched_counted(None, None, 1, fake, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_intersect_batched_counted(fake, None, 1, None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert "counters" in L.ccs_last_error().decode()
+    # the entry point that allocates nothing refuses rows beyond its scratch before any device call
+    assert L.ccs_policy_grad_noalloc(None, fake, fake, 4, 0, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
+    n = ccs.GRAD_NOALLOC_MAX_ROWS + 1
+    assert L.ccs_policy_grad_noalloc(fake, fake, fake, n, 0, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
+    assert "scratch" in L.ccs_last_error().decode()
