@@ -202,9 +202,13 @@ class Scene:
                                    _p(cnt, C.c_uint32))
         return dict(t=t, id=ids, u=u, v=v, counters=cnt)
 
-    def intersect_single_box(self, rays, nthreads: int = 0):
-        """Closest hits and counters when every subdivision node tests only its own box
-        (Sec. 3.3's alternative to the two-box test): dict(t, id, u, v, counters)."""
+    def intersect_retest(self, rays, nthreads: int = 0):
+        """Closest hits and counters when a pending sibling is skipped on resumption if its
+        box's entry (tested when its parent was split) lies beyond the best distance found
+        since; Alg. 3 resumes it without re-testing.  dict(t, id, u, v, counters)."""
+        return self._mode(rays, 3, nthreads)
+
+    def _mode(self, rays, mode, nthreads):
         r = np.ascontiguousarray(rays, dtype=np.float32).reshape(-1, 8)
         n = r.shape[0]
         zero = np.zeros(n)
@@ -212,10 +216,15 @@ class Scene:
         t, u, v = np.zeros(n), np.zeros(n), np.zeros(n)
         ids = np.zeros(n, dtype=np.uint32)
         cnt = np.zeros((n, 8), dtype=np.uint32)
-        lib().orc_intersect_hinted(self._h, _p(r, C.c_float), n, nthreads, 2, _p(hid, C.c_uint32), _p(zero, C.c_double),
-                                   _p(zero, C.c_double), _p(t, C.c_double), _p(ids, C.c_uint32), _p(u, C.c_double),
-                                   _p(v, C.c_double), _p(cnt, C.c_uint32))
+        lib().orc_intersect_hinted(self._h, _p(r, C.c_float), n, nthreads, mode, _p(hid, C.c_uint32),
+                                   _p(zero, C.c_double), _p(zero, C.c_double), _p(t, C.c_double),
+                                   _p(ids, C.c_uint32), _p(u, C.c_double), _p(v, C.c_double), _p(cnt, C.c_uint32))
         return dict(t=t, id=ids, u=u, v=v, counters=cnt)
+
+    def intersect_single_box(self, rays, nthreads: int = 0):
+        """Closest hits and counters when every subdivision node tests only its own box
+        (Sec. 3.3's alternative to the two-box test): dict(t, id, u, v, counters)."""
+        return self._mode(rays, 2, nthreads)
 
     def _trace(self, fn, patch, ray8, cap, max_seq):
         r = np.ascontiguousarray(ray8, dtype=np.float32).reshape(8)

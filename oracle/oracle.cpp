@@ -350,7 +350,10 @@ struct Split {
 //               own domain by Alg. 2, with its own displacement); a hit node above
 //               the leaf depth has both halves visited, the lower one first, and a
 //               hit leaf is recorded at its own entry distance.
-enum OrderMode { kHindsight = 0, kLookahead = 1, kSingleBox = 2 };
+//   kRetest:    closest-first, and a pending sibling is skipped when it is resumed if its
+//               box (tested when its parent was split) is entered beyond the best distance
+//               found since (Alg. 3 does not re-test it; measurement of what that would save).
+enum OrderMode { kHindsight = 0, kLookahead = 1, kSingleBox = 2, kRetest = 3 };
 struct OrderHint {
   int mode;
   uint32_t id, pu, pv;
@@ -371,6 +374,7 @@ struct Frame {
   uint32_t pu, pv, su, sv;
   int axis, depth;
   bool second;
+  double entry;  // entry distance of the frame's box, tested when its parent was split
   Grid g;
   V3 d;
 };
@@ -381,8 +385,8 @@ static void run_frames(const Patch& P, uint32_t id, const Ray& r, int L, Best& b
 // The two children of frame f (first = ch[0]) in the order first_r gives; the first
 // one gets its Gregory grid (the recompute of Alg. 3), the second is pushed for later.
 static void push_children(const Patch& P, const Frame& f, const Grid& gl, const Grid& gr, bool hl, bool hr,
-                          bool first_r, uint32_t rpu, uint32_t rpv, uint32_t csu, uint32_t csv, Counters& c,
-                          std::vector<Frame>& stack) {
+                          bool first_r, uint32_t rpu, uint32_t rpv, uint32_t csu, uint32_t csv, double tl, double tr,
+                          Counters& c, std::vector<Frame>& stack) {
   Frame ch[2];
   for (int k = 0; k < 2; ++k) {
     bool is_r = (k == 0) ? first_r : !first_r;
@@ -394,6 +398,7 @@ static void push_children(const Patch& P, const Frame& f, const Grid& gl, const 
     n.axis = 1 - f.axis;
     n.depth = f.depth + 1;
     n.second = (k == 1);
+    n.entry = is_r ? tr : tl;
     n.g = is_r ? gr : gl;
     n.d = {0, 0, 0};
   }
@@ -456,6 +461,7 @@ static void intersect_patch(const Patch& P, uint32_t id, const Ray& r, int L, Be
   root.axis = 0;
   root.depth = 0;
   root.second = false;
+  root.entry = 0.0;
   if (P.gregory) {
     Bound b = calc_points_and_d_int(P, 0, 0, kFull, kFull);
     c.greg++;
@@ -475,6 +481,7 @@ static void run_frames(const Patch& P, uint32_t id, const Ray& r, int L, Best& b
   while (!stack.empty()) {
     Frame f = stack.back();
     stack.pop_back();
+    if (f.second && hint && hint->mode == kRetest && f.entry > best.t) continue;  // behind the best hit
     if (f.second) {
       c.backtrack++;
       if (!P.gregory) c.crop++;  // Alg. 3 re-crops a Bezier grid after backtracking
@@ -507,7 +514,7 @@ static void run_frames(const Patch& P, uint32_t id, const Ray& r, int L, Best& b
         std::vector<Frame> sub;
         Best b2 = best;
         Counters c2 = {0, 0, 0, 0, 0, 0, 0, 0};
-        push_children(P, f, gl, gr, hl, hr, o == 0 ? first_r : !first_r, rpu, rpv, csu, csv, c2, sub);
+        push_children(P, f, gl, gr, hl, hr, o == 0 ? first_r : !first_r, rpu, rpv, csu, csv, tl, tr, c2, sub);
         run_frames(P, id, r, L, b2, c2, nullptr, nullptr, sub);
         steps[o] = c2.split;
       }
@@ -525,7 +532,7 @@ static void run_frames(const Patch& P, uint32_t id, const Ray& r, int L, Best& b
       }
       continue;
     }
-    push_children(P, f, gl, gr, hl, hr, first_r, rpu, rpv, csu, csv, c, stack);
+    push_children(P, f, gl, gr, hl, hr, first_r, rpu, rpv, csu, csv, tl, tr, c, stack);
   }
 }
 
@@ -1032,7 +1039,7 @@ void orc_intersect_hinted(void* s, const float* rays, uint32_t n, int nthreads, 
     h.id = hint_id[i];
     h.pu = std::min((uint32_t)(hint_u[i] / kUnit) & ~(leaf - 1), kFull - leaf);
     h.pv = std::min((uint32_t)(hint_v[i] / kUnit) & ~(leaf - 1), kFull - leaf);
-    trace_ray(S, r, b, c, (mode == kHindsight && h.id == kNoHit) ? nullptr : &h);  // kSingleBox ignores the hint
+    trace_ray(S, r, b, c, (mode == kHindsight && h.id == kNoHit) ? nullptr : &h);  // other modes ignore the hint
     t[i] = b.t;
     id[i] = b.id;
     u[i] = b.u;
