@@ -37,10 +37,10 @@ def test_bit_trail_loop_visits_the_recursion_sequence(c1, oracle_any):
     """Alg. 3 (pos/size/trail registers, ctz backtracking) and the explicit-stack
     recursion produce identical split sequences and hits on random ray-patch pairs."""
     rng = np.random.default_rng(11)
-    rays, idx = rays_at_patches(c1.cp, c1.types, 6000, rng)
+    rays, idx = rays_at_patches(c1.cp, c1.types, 60000, rng)
     greg = np.where(c1.types == 1)[0]
-    # weight Gregory patches up
-    rays2, idx2 = rays_at_patches(c1.cp[greg], c1.types[greg], 4000, rng)
+    # weight Gregory patches up (10^5 pairs in all)
+    rays2, idx2 = rays_at_patches(c1.cp[greg], c1.types[greg], 40000, rng)
     rays = np.concatenate([rays, rays2])
     idx = np.concatenate([idx, greg[idx2]])
     caps = np.where(rng.uniform(size=len(rays)) < 0.3, rng.uniform(0.5, 3.0, size=len(rays)), np.inf)
@@ -54,7 +54,7 @@ def test_bit_trail_loop_visits_the_recursion_sequence(c1, oracle_any):
         assert ha[0] == hb[0] or abs(ha[0] - hb[0]) <= 1e-12 * max(1.0, abs(ha[0])), k
         n_steps += len(a)
         n_hits += ha[1] != O.NO_HIT
-    assert n_hits > 1000 and n_steps > 50000
+    assert n_hits > 10000 and n_steps > 500000
 
 
 def test_counters_are_consistent(c1, c1_oracle):
