@@ -74,15 +74,13 @@ def test_counters_are_consistent(c1, c1_oracle):
 def test_dense_tessellation_agrees_within_the_method_error_bound(c1, oracle_any):
     c1_oracle = oracle_any
     L = c1.leaf_depth
-    sel_p = S.sample_indices(len(c1.primary), 768, seed=5)
-    sel_d = S.sample_indices(len(c1.diffuse), 768, seed=6)
-    rays = np.concatenate([c1.primary[sel_p], c1.diffuse[sel_d]])
+    rays = np.concatenate([c1.primary, c1.diffuse])  # every ray of the torus workload
     o = c1_oracle.intersect(rays)
     bf = c1_oracle.bruteforce(rays, res=512)
     eps_tess = 1e-6 * c1.diameter
     hit_o = o["id"] != O.NO_HIT
     hit_b = bf["id"] != O.NO_HIT
-    assert hit_b.sum() > 500
+    assert hit_b.sum() > 10000
     # (i) no false negatives: a surface hit always has a method hit at or before it
     assert np.all(hit_o[hit_b])
     assert np.all(o["t"][hit_b] <= bf["t"][hit_b] + eps_tess)
@@ -120,7 +118,7 @@ def test_dense_tessellation_agrees_within_the_method_error_bound(c1, oracle_any)
         du = max(0.0, abs(o["u"][k] - ub) - leaf / 2)
         dv = max(0.0, abs(o["v"][k] - vb) - leaf / 2)
         assert np.hypot(du, dv) <= 1.5 * (gap * np.linalg.norm(d) + diag) / smin + 1e-9, k
-    assert good > 400
+    assert good > 8000
 
 
 def test_rays_through_shared_edges_and_corners_never_miss(c1, oracle_any):
