@@ -149,3 +149,25 @@ def test_direction_magnitude(ccs, c1, scale):
     assert_gate(gate(g, o, rays, osc, c1.diameter / scale, c1.leaf_depth, label=f"|d| x {scale:g}"))
     hit = ids_of(g) != O.NO_HIT
     assert hit.sum() > 1000 and np.isfinite(g[hit]).all()
+
+
+@pytest.mark.parametrize("local", [False, True], ids=["world", "local"])
+def test_gregory_patches_with_coincident_pairs_intersect_as_bezier(ccs, c1, local):
+    """Every torus patch tagged Gregory with P^v = P^u (Sec. 3.2: then it is its Bézier
+    patch): the GPU recomputes such a patch's grid at every node (Alg. 3) where the
+    Bézier path splits it, so the fp32 boxes differ by rounding; the same patch and
+    leaf on >= 99.99 % of the rays, and both scenes pass the gate against the oracle."""
+    cp = c1.cp.copy()
+    cp[:, 16:20] = cp[:, [5, 6, 9, 10]]
+    rays = np.concatenate([c1.primary, c1.diffuse])
+    hits = {}
+    for tag in (1, 0):
+        ty = np.full(len(cp), tag, np.uint8)
+        gsc, osc = _both(ccs, cp, ty, c1.leaf_depth, local)
+        hits[tag] = _run(gsc, rays)
+        assert_gate(gate(hits[tag], osc.intersect(rays), rays, osc, c1.diameter, c1.leaf_depth,
+                         label=f"coincident-pairs-tag{tag}"))
+    g, b = hits[1], hits[0]
+    same = (ids_of(g) == ids_of(b)) & (g[:, 2] == b[:, 2]) & (g[:, 3] == b[:, 3])
+    _say(f"Gregory-tagged vs Bezier-tagged: same patch and leaf on {same.mean():.6f} of {len(rays)} rays")
+    assert same.mean() >= 0.9999

@@ -210,3 +210,23 @@ def test_bounce_directions_are_cosine_weighted():
     np.testing.assert_allclose(np.linalg.norm(out[:, 4:7], axis=1), 1.0, atol=1e-6)
     # cosine-weighted: E[cos] = 2/3, E[cos^2] = 1/2
     assert abs(cz.mean() - 2 / 3) < 0.01 and abs((cz ** 2).mean() - 0.5) < 0.01
+
+
+def test_gregory_patches_with_coincident_pairs_intersect_as_bezier(c1, oracle_any):
+    """A Gregory patch whose paired inner points coincide is its Bézier patch (Sec. 3.2):
+    on the torus with every patch tagged Gregory and P^v = P^u, Alg. 2 gives d = 0
+    and the Bézier lower grid on every domain, so every ray gets the hit of the same
+    scene tagged Bézier (same patch and leaf; t to the rounding of a crop against a
+    split grid)."""
+    cp = c1.cp.copy()
+    cp[:, 16:20] = cp[:, [5, 6, 9, 10]]
+    rays = np.concatenate([c1.primary, c1.diffuse])
+    res = []
+    for tag in (1, 0):
+        osc = O.Scene(cp, np.full(len(cp), tag, np.uint8), c1.leaf_depth, local_frames=oracle_any.local_frames)
+        res.append(osc.intersect(rays))
+    g, b = res
+    hit = b["id"] != O.NO_HIT
+    assert hit.sum() > 10000
+    assert np.array_equal(g["id"], b["id"]) and np.array_equal(g["u"], b["u"]) and np.array_equal(g["v"], b["v"])
+    assert np.allclose(g["t"][hit], b["t"][hit], rtol=1e-12, atol=1e-14)
