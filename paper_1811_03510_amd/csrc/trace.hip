@@ -35,6 +35,7 @@
 #include "ccs_internal.h"
 #include "patch_math.h"
 #include "policy.h"
+#include "ray_valid.h"
 
 namespace ccs {
 
@@ -47,8 +48,6 @@ struct Counts {
   uint32_t node, cand, split, backtrack, greg, leaf, crop, cand_greg;
 };
 
-__device__ __forceinline__ bool finite_bits(float x) { return (__float_as_uint(x) & 0x7F800000u) != 0x7F800000u; }
-__device__ __forceinline__ bool nan_bits(float x) { return (__float_as_uint(x) & 0x7FFFFFFFu) > 0x7F800000u; }
 
 // Batch of launch ray k (a wave-uniform scan: the table is never indexed per lane).
 __device__ __forceinline__ uint32_t batch_of(const BatchTable& bt, uint32_t k) {
@@ -167,11 +166,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
           recs = s.recs + (size_t)frame * s.frame_rec_floats;
           const float4* r4 = reinterpret_cast<const float4*>(rays + local);
           const float4 ro = r4[0], rd = r4[1];
-          // integer bit tests: this file is compiled assuming no NaN
-          const bool finite = finite_bits(ro.x) && finite_bits(ro.y) && finite_bits(ro.z) && finite_bits(rd.x) &&
-                              finite_bits(rd.y) && finite_bits(rd.z) && !nan_bits(ro.w) && !nan_bits(rd.w);
-          const bool valid = finite && !(rd.x == 0.0f && rd.y == 0.0f && rd.z == 0.0f) && ro.w <= rd.w &&
-                             s.n_nodes > 0;
+          const bool valid = ray_traced(ro, rd) && s.n_nodes > 0;
           best_t = rd.w;
           best_id = kNoHit;
           if (kStats) cnt = Counts{0, 0, 0, 0, 0, 0, 0, 0};
