@@ -240,6 +240,24 @@ ccs_status ccs_bounce(const ccs_scene* scene, const ccs_ray* rays, const ccs_hit
 ccs_status ccs_bounce_frame(const ccs_scene* scene, uint32_t frame, const ccs_ray* rays, const ccs_hit* hits,
                             const float* uniforms, uint32_t n, ccs_ray* out_rays, void* stream);
 
+/* Stream compaction of a ray array for path tracing (Sec. 4: each bounce level
+ * traces the reflection rays of the previous level's hits; a bounce of a missed
+ * ray is inactive, so later levels hold few active rays among many).  Copies the
+ * rays of rays[0, n) that the intersection entry points trace -- finite origin
+ * and direction, tmin and tmax not NaN, a nonzero direction and tmin <= tmax,
+ * decided with fp32 denormals flushed to zero as the intersection kernel does --
+ * to out_rays[0, m) in their input order, writes the input index of out_rays[k]
+ * to out_index[k], and m to work[0].  Every other ray would be returned as a miss
+ * by an intersection entry point.  `work` is caller-owned device memory of
+ * CCS_COMPACT_WORK_WORDS(n) uint32 (word 0 the count, the rest the scan's
+ * per-block counts); the library allocates nothing, so calls with different
+ * `work` buffers may run concurrently.  All pointers are device pointers; out_rays
+ * and out_index hold up to n elements and may not alias rays.  Asynchronous on
+ * `stream`: read m after the stream has reached the call.  n = 0 sets work[0] = 0. */
+#define CCS_COMPACT_WORK_WORDS(n) (1u + (uint32_t)(((uint64_t)(n) + 255u) / 256u))
+ccs_status ccs_compact_rays(const ccs_ray* rays, uint32_t n, ccs_ray* out_rays, uint32_t* out_index, uint32_t* work,
+                            void* stream);
+
 /* Measurement of the fp32 grid arithmetic (Sec. 3.4 compares control points
  * recomputed for a subdomain with those reached by repeated subdivision).  For
  * query k: patch patch_ids[k] (index into the creation arrays), the subdomain

@@ -24,8 +24,10 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
 TRACE_FLAGS = ["-mno-amdgpu-ieee", "-fno-honor-nans", "-fgpu-flush-denormals-to-zero", "-fno-signed-zeros",
                "-ffp-contract=off"]
-# policy.hip forms the learned order's inputs exactly as the intersection kernel does
-PER_FILE = {"trace.hip": TRACE_FLAGS, "policy.hip": TRACE_FLAGS, "refit.hip": ["-ffp-contract=off"]}
+# policy.hip forms the learned order's inputs exactly as the intersection kernel does, and
+# compact.hip decides which rays are traced exactly as the intersection kernel does
+PER_FILE = {"trace.hip": TRACE_FLAGS, "policy.hip": TRACE_FLAGS, "compact.hip": TRACE_FLAGS,
+            "refit.hip": ["-ffp-contract=off"]}
 
 
 def sources():

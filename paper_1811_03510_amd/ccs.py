@@ -28,7 +28,7 @@ EXPORTS = ("ccs_scene_create", "ccs_refit", "ccs_intersect", "ccs_intersect_coun
            "ccs_scene_get_launch", "ccs_scene_set_frames", "ccs_refit_frame", "ccs_intersect_batched",
            "ccs_scene_set_policy", "ccs_policy_record", "ccs_policy_infer", "ccs_policy_grad", "ccs_policy_train",
            "ccs_bounce_frame", "ccs_device_bytes_in_use", "ccs_debug_grids", "ccs_policy_grad_noalloc",
-           "ccs_intersect_batched_counted")
+           "ccs_intersect_batched_counted", "ccs_compact_rays")
 MAX_BATCHES = 32
 MAX_RAYS = (1 << 31) - 1  # per call
 POLICY_PARAMS = 1732
@@ -109,6 +109,7 @@ def lib():
         L.ccs_policy_grad_noalloc.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp]
         L.ccs_policy_train.argtypes = [vp, vp, vp, u32, C.POINTER(TrainParams), C.POINTER(AdamState), vp, vp]
         L.ccs_debug_grids.argtypes = [vp, u32, vp, vp, vp, u32, vp, vp]
+        L.ccs_compact_rays.argtypes = [vp, u32, vp, vp, vp, vp]
         L.ccs_device_bytes_in_use.argtypes = []
         for name in EXPORTS:
             if name not in ("ccs_scene_destroy", "ccs_last_error", "ccs_device_bytes_in_use"):
@@ -325,6 +326,38 @@ class Scene:
             raise ValueError("out must not alias rays")
         _check(lib().ccs_bounce_frame(self._h, int(frame), _ptr(r), _ptr(h), _ptr(u), n, _ptr(out), _stream(stream)))
         return out
+
+
+def compact_work_words(n: int) -> int:
+    """Words of the workspace ccs_compact_rays needs for n rays (CCS_COMPACT_WORK_WORDS)."""
+    return 1 + (int(n) + 255) // 256
+
+
+def compact_rays(rays, out=None, index=None, work=None, stream=None):
+    """The rays the intersection entry points trace, in input order (ccs_compact_rays).
+
+    rays: (N, 8) float32 CUDA tensor.  out (>= N, 8) float32, index (>= N,) int32 (uint32
+    bits) and work (>= compact_work_words(N),) int32 are allocated when not given.  Returns
+    (out, index, work); the count m is work[0] (device): out[:m] and index[:m] are valid once
+    the stream has reached the call."""
+    import torch
+    r = Scene._rays(rays)
+    n = r.shape[0]
+    if out is None:
+        out = torch.empty_like(r)
+    if index is None:
+        index = torch.empty(n, dtype=torch.int32, device=r.device)
+    if work is None:
+        work = torch.empty(compact_work_words(n), dtype=torch.int32, device=r.device)
+    for t, name, dt, ok in ((out, "out", torch.float32, out.dim() == 2 and out.shape[1] == 8 and out.shape[0] >= n),
+                            (index, "index", torch.int32, index.dim() == 1 and index.numel() >= n),
+                            (work, "work", torch.int32, work.dim() == 1 and work.numel() >= compact_work_words(n))):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and ok):
+            raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of sufficient size")
+    if n > 0 and out.data_ptr() == r.data_ptr():
+        raise ValueError("out must not alias rays")
+    _check(lib().ccs_compact_rays(_ptr(r), n, _ptr(out), _ptr(index), _ptr(work), _stream(stream)))
+    return out, index, work
 
 
 def _out(t, n: int, width: int, dtype, name: str):

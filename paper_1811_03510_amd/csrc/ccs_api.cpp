@@ -632,6 +632,19 @@ ccs_status ccs_bounce(const ccs_scene* s, const ccs_ray* rays, const ccs_hit* hi
   return ccs_bounce_frame(s, 0, rays, hits, uniforms, n, out_rays, stream);
 }
 
+ccs_status ccs_compact_rays(const ccs_ray* rays, uint32_t n, ccs_ray* out_rays, uint32_t* out_index, uint32_t* work,
+                            void* stream) {
+  g_error.clear();
+  if (!work) return fail(CCS_ERR_INVALID_ARG, "work is NULL");
+  if (n > 0 && (!rays || !out_rays || !out_index)) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if (n > 0 && (const void*)out_rays == (const void*)rays) return fail(CCS_ERR_INVALID_ARG, "out_rays aliases rays");
+  if (((uintptr_t)rays | (uintptr_t)out_rays) % 16 != 0 || ((uintptr_t)out_index | (uintptr_t)work) % 4 != 0)
+    return fail(CCS_ERR_INVALID_ARG, "rays and out_rays must be 16-byte aligned, out_index and work 4-byte aligned");
+  hipError_t e = ccs::launch_compact_rays(rays, n, out_rays, out_index, work, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "compaction launch");
+  return CCS_OK;
+}
+
 ccs_status ccs_debug_grids(const ccs_scene* s, uint32_t frame, const uint32_t* patch_ids, const uint32_t* codes,
                            const uint32_t* depths, uint32_t n, float* out, void* stream) {
   g_error.clear();

@@ -98,5 +98,9 @@ hipError_t launch_debug_grids(const DeviceScene& s, const uint32_t* patch, const
                               const uint32_t* depth, uint32_t n, float* out, hipStream_t stream);
 hipError_t launch_bounce(const DeviceScene& s, const ccs_ray* rays, const ccs_hit* hits, const float* uniforms,
                          uint32_t n, ccs_ray* out, hipStream_t stream);
+// Ray compaction (compact.hip): blocks of 256 rays; work holds 1 + compact_blocks(n) words.
+inline uint32_t compact_blocks(uint32_t n) { return (uint32_t)(((uint64_t)n + 255u) / 256u); }
+hipError_t launch_compact_rays(const ccs_ray* rays, uint32_t n, ccs_ray* out, uint32_t* index, uint32_t* work,
+                               hipStream_t stream);
 
 }  // namespace ccs

@@ -152,3 +152,17 @@ def test_measurement_and_noalloc_entry_points_validate_on_the_host():
     n = ccs.GRAD_NOALLOC_MAX_ROWS + 1
     assert L.ccs_policy_grad_noalloc(fake, fake, fake, n, 0, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
     assert "scratch" in L.ccs_last_error().decode()
+
+
+def test_compaction_validates_on_the_host():
+    L = ccs.lib()
+    fake, other = C.c_void_p(16), C.c_void_p(4096)  # never dereferenced: each call fails validation first
+    assert L.ccs_compact_rays(fake, 4, other, fake, None, None) == ccs.CCS_ERR_INVALID_ARG
+    assert "work" in L.ccs_last_error().decode()
+    assert L.ccs_compact_rays(None, 4, other, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
+    assert L.ccs_compact_rays(fake, 4, fake, other, other, None) == ccs.CCS_ERR_INVALID_ARG
+    assert "alias" in L.ccs_last_error().decode()
+    assert L.ccs_compact_rays(C.c_void_p(24), 4, other, fake, fake, None) == ccs.CCS_ERR_INVALID_ARG
+    assert "aligned" in L.ccs_last_error().decode()
+    # the workspace: the count and one word per block of 256 rays
+    assert [ccs.compact_work_words(n) for n in (0, 1, 256, 257, 2**32 - 1)] == [1, 2, 2, 3, 1 + 2**24]
