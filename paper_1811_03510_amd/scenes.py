@@ -414,7 +414,10 @@ def animate(cp: np.ndarray, frame: int, n_frames: int = 16, seed: int = STREAM_A
 
     def one(b):
         x = cp[b:b + chunk].astype(np.float64).reshape(-1, 3)
-        arg = x @ k.T + phase[None, :] + 2.0 * np.pi * frame / n_frames
+        # k . x as elementwise products and sums: a matrix product here would go to BLAS,
+        # whose concurrent calls from the pool's threads have given corrupted results
+        arg = np.stack([(x[:, 0] * k[i, 0] + x[:, 1] * k[i, 1]) + x[:, 2] * k[i, 2] for i in range(3)], axis=1)
+        arg = arg + phase[None, :] + 2.0 * np.pi * frame / n_frames
         out[b:b + chunk] = (x + amp * np.sin(arg)).reshape(-1, 20, 3).astype(np.float32)
 
     from concurrent.futures import ThreadPoolExecutor  # elementwise: any chunk order gives the same bits
@@ -501,7 +504,7 @@ class Combined:
         return animate(self.cp, f, self.n_frames)
 
     def bounce_uniforms(self, frame: int, bounce: int, n: int) -> np.ndarray:
-        """Seeded uniforms (n x 2) for secondary-ray generation (ccs_bounce)."""
+        """Seeded uniforms for secondary-ray generation (ccs_bounce): 2 n values, pair i for ray i."""
         return uniform(substream(STREAM_BOUNCE, 1000 + 16 * frame + bounce), 2 * n).astype(np.float32)
 
     @property
