@@ -61,7 +61,7 @@ def log(*a):
 # it includes, and the build script that holds its compiler flags.
 KERNEL_SOURCES = ("paper_1811_03510_amd/csrc/trace.hip", "paper_1811_03510_amd/csrc/patch_math.h",
                   "paper_1811_03510_amd/csrc/ccs_internal.h", "paper_1811_03510_amd/csrc/policy.h",
-                  "include/ccs.h", "paper_1811_03510_amd/build.py")
+                  "paper_1811_03510_amd/csrc/ray_valid.h", "include/ccs.h", "paper_1811_03510_amd/build.py")
 
 
 def source_hash() -> str:

@@ -3,8 +3,8 @@
 // nonzero direction and tmin <= tmax.  Both files are compiled assuming no NaN
 // arithmetic, and the optimizer turns mask-and-compare tests on a float's bits
 // into floating-point classifications, which that assumption then lets it
-// simplify (a NaN would pass as finite).  So the bits pass through an empty asm
-// statement first, which the optimizer cannot see through: the tests stay
+// simplify (a NaN would pass as finite).  So the tested integers pass through an
+// empty asm statement, which the optimizer cannot see through: the tests stay
 // integer tests on the stored bits.
 #pragma once
 
@@ -13,20 +13,21 @@
 
 namespace ccs {
 
-__device__ __forceinline__ uint32_t opaque_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  asm volatile("" : "+v"(u));
-  return u;
-}
-__device__ __forceinline__ bool finite_bits(float x) { return (opaque_bits(x) & 0x7F800000u) != 0x7F800000u; }
-__device__ __forceinline__ bool nan_bits(float x) { return (opaque_bits(x) & 0x7FFFFFFFu) > 0x7F800000u; }
+__device__ __forceinline__ uint32_t bits(float x) { return __float_as_uint(x); }
 
-// ro = (origin, tmin), rd = (direction, tmax).  The comparisons run after the NaN
-// tests, with the kernel's fp32 denormals flushed to zero.
+// ro = (origin, tmin), rd = (direction, tmax).  A component is infinite or NaN iff its
+// exponent field is all ones, so the origin and direction are finite iff the largest
+// of their six exponent fields is not; tmin and tmax are not NaN iff neither
+// magnitude exceeds infinity's.  The two integers go through the asm statement; the
+// comparisons that follow run after those tests, with fp32 denormals flushed to zero
+// as in the intersection kernel.
 __device__ __forceinline__ bool ray_traced(const float4& ro, const float4& rd) {
-  const bool finite = finite_bits(ro.x) && finite_bits(ro.y) && finite_bits(ro.z) && finite_bits(rd.x) &&
-                      finite_bits(rd.y) && finite_bits(rd.z) && !nan_bits(ro.w) && !nan_bits(rd.w);
-  return finite && !(rd.x == 0.0f && rd.y == 0.0f && rd.z == 0.0f) && ro.w <= rd.w;
+  constexpr uint32_t kExp = 0x7F800000u, kMag = 0x7FFFFFFFu;
+  uint32_t e = max(max(max(bits(ro.x) & kExp, bits(ro.y) & kExp), max(bits(ro.z) & kExp, bits(rd.x) & kExp)),
+                   max(bits(rd.y) & kExp, bits(rd.z) & kExp));
+  uint32_t t = max(bits(ro.w) & kMag, bits(rd.w) & kMag);
+  asm volatile("" : "+v"(e), "+v"(t));
+  return e != kExp && t <= kExp && !(rd.x == 0.0f && rd.y == 0.0f && rd.z == 0.0f) && ro.w <= rd.w;
 }
 
 }  // namespace ccs
