@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from oracle.parity import assert_gate, gate
+from oracle.parity import assert_gate, gate, ids_of
 from paper_1811_03510_amd import scenes as S
 
 torch = pytest.importorskip("torch")
@@ -302,6 +302,23 @@ def test_combined_pipeline_at_one_million_patches():
     torch.cuda.synchronize()
     for f in range(F):
         assert np.array_equal(hc[f].cpu().numpy().view(np.uint32), h0[f].cpu().numpy().view(np.uint32))
+    # the bounce level compacted to its active rays (ccs_compact_rays) and traced in one batched
+    # launch gives, closest-first, the full level's hits at the kept rays and misses elsewhere
+    full = sc.intersect_batched([(f, brays[f], None) for f in range(F)])
+    packed = [ccs.compact_rays(brays[f]) for f in range(F)]
+    torch.cuda.synchronize()
+    m = [int(wk[0].item()) for _, _, wk in packed]
+    part = sc.intersect_batched([(f, packed[f][0][:m[f]], None) for f in range(F)])
+    torch.cuda.synchronize()
+    for f in range(F):
+        idx = packed[f][1][:m[f]].cpu().numpy()
+        fh = full[f].cpu().numpy()
+        _say(f"1M combined: frame {f}, bounce level compacted to {m[f]} of {len(fh)} rays")
+        assert 0.2 * len(fh) < m[f] < len(fh)
+        assert np.array_equal(part[f].cpu().numpy().view(np.uint32), fh[idx].view(np.uint32))
+        rest = np.ones(len(fh), bool)
+        rest[idx] = False
+        assert (ids_of(fh[rest]) == O.NO_HIT).all()
     for f in range(F):
         osc = O.Scene(frames[f], w.types, w.leaf_depth, local_frames=True)
         for lvl, (r, h) in enumerate(((prim, h0[f]), (brays[f], h1[f]))):
