@@ -363,7 +363,7 @@ def affine_patch(a, e1, e2):
     return g
 
 
-@pytest.mark.parametrize("L", [3, 7, 12])
+@pytest.mark.parametrize("L", [3, 7, 12, 17, 22])
 def test_affine_patch_closed_form(L):
     """f = a + u e1 + v e2 exactly (degree elevation of a plane).  With (u*, v*, t*) the
     closed-form ray/plane solution, the reported hit obeys the method's error bound:
@@ -372,8 +372,13 @@ def test_affine_patch_closed_form(L):
     rng = np.random.default_rng(L)
     checked = 0
     for trial in range(60):
-        g = affine_patch(rng.normal(size=3), rng.normal(size=3), rng.normal(size=3))
+        # a and the per-index steps e1 / 3, e2 / 3 on a 2^-10 grid: every control point
+        # a + i e1/3 + j e2/3 is exact in fp32, so the patch is exactly the plane even at
+        # leaf depths where rounding a point off the plane would exceed a leaf's thickness
+        a, q1, q2 = (np.round(rng.normal(size=3) * 1024.0) / 1024.0 for _ in range(3))
+        g = np.array([a + i * q1 + j * q2 for j in range(4) for i in range(4)])
         cp = np.concatenate([g, g[[5, 6, 9, 10]]]).astype(np.float32)
+        assert np.array_equal(cp.astype(np.float64), np.concatenate([g, g[[5, 6, 9, 10]]]))
         sc = O.Scene(cp[None], np.array([trial % 2], np.uint8), L)
         c64 = cp.astype(np.float64)
         a32, e1, e2 = c64[0], c64[3] - c64[0], c64[12] - c64[0]
