@@ -46,7 +46,14 @@ extern "C" {
 #endif
 
 #define CCS_NO_HIT 0xFFFFFFFFu
-#define CCS_MAX_LEAF_DEPTH 16
+/* Per-axis leaf depth L.  Alg. 3's domains (units of 2^-23) would allow 22, but the
+ * fp32 subdivision's rounding, a few ulps of the patch's extent after 40 splits,
+ * then exceeds a leaf box (2^-22 of the extent): at L = 22 rays were measured to
+ * pass through surfaces.  Up to 16 the intersection kernels keep a domain's path and
+ * trail in 32-bit words; from 17 to 20 in 64-bit words, closest-first order only:
+ * the learned order (ccs_scene_set_policy), the single-box ablation
+ * (CCS_FLAG_SINGLE_BOX) and ccs_debug_grids return CCS_ERR_UNSUPPORTED there. */
+#define CCS_MAX_LEAF_DEPTH 20
 /* Scene flag: subdivide every patch in its own frame (Sec. 3.4: boxes in patch-local
  * frames overlap less, so fewer subdomains survive the slab tests).  The frame of a
  * patch has rows r0 = unit(p30 - p00), r1 = unit of (p03 - p00) with its r0 part
@@ -67,7 +74,7 @@ extern "C" {
  * Sec. 3.3 reports that the two-box test nearly halves the traversal time against
  * this.  Results obey the same contract (closest leaf box hit; a Gregory leaf box
  * is then the leaf's own bound).  Closest-first only: ccs_scene_set_policy
- * returns CCS_ERR_UNSUPPORTED on such a scene. */
+ * returns CCS_ERR_UNSUPPORTED on such a scene; leaf depths up to 16. */
 #define CCS_FLAG_SINGLE_BOX 2u
 
 typedef enum ccs_status {
@@ -104,7 +111,7 @@ typedef struct ccs_scene_desc {
   const uint8_t* patch_types;   /* n tags; same location as control_points */
   uint32_t n_patches;           /* 0 <= n < 2^31; an empty scene makes every ray miss */
   int32_t location;             /* CCS_HOST or CCS_DEVICE */
-  uint32_t leaf_depth;          /* L, 1..16 */
+  uint32_t leaf_depth;          /* L, 1..CCS_MAX_LEAF_DEPTH (20) */
   uint32_t flags;               /* 0, or CCS_FLAG_LOCAL_FRAMES and/or CCS_FLAG_SINGLE_BOX */
   void* stream;                 /* hipStream_t used for the uploads */
 } ccs_scene_desc;
@@ -262,7 +269,8 @@ ccs_status ccs_compact_rays(const ccs_ray* rays, uint32_t n, ccs_ray* out_rays, 
  * recomputed for a subdomain with those reached by repeated subdivision).  For
  * query k: patch patch_ids[k] (index into the creation arrays), the subdomain
  * reached by depths[k] splits (u first, alternating) whose halves are the bits of
- * codes[k] (split s owns bit 2L-1-s, set for the upper half; no other bits set).
+ * codes[k] (split s owns bit 2L-1-s, set for the upper half; no other bits set;
+ * scenes with L <= 16, CCS_ERR_UNSUPPORTED above).
  * out (n x CCS_DEBUG_GRID_FLOATS fp32) row k holds, as stored on `frame`
  * (anchored, and mapped into the patch frame with CCS_FLAG_LOCAL_FRAMES):
  *   [0, 60)    the patch's stored points: x, y, z of slots 0..15, then of the P^v;
@@ -306,7 +314,8 @@ ccs_status ccs_debug_grids(const ccs_scene* scene, uint32_t frame, const uint32_
  * scene: later ccs_intersect* calls use the learned order.  NULL detaches it
  * (closest-first order).  The weights are packed on `stream`; params may be
  * freed once the stream has passed the call.  CCS_ERR_UNSUPPORTED when the
- * scene's BVH is deeper than 31 levels (the learned kernel's node stack). */
+ * scene's BVH is deeper than 31 levels (the learned kernel's node stack) or its
+ * leaf depth above 16. */
 ccs_status ccs_scene_set_policy(ccs_scene* scene, const float* params, void* stream);
 
 /* Training records for n rays and their hits on frame 0 (device pointers).

@@ -139,7 +139,7 @@ class Scene:
     """A patch scene on the current GPU.
 
     control_points: (n, 20, 3) float32 (torch tensor on cuda or cpu, or numpy);
-    patch_types: (n,) uint8 (0 Bezier, 1 Gregory); leaf_depth: L in [1, 16].
+    patch_types: (n,) uint8 (0 Bezier, 1 Gregory); leaf_depth: L in [1, 20] (above 16: closest-first order only).
     local_frames: subdivide in patch-local frames; single_box: the one-box-per-step
     ablation of Sec. 3.3 (measurement only).
     """

@@ -239,11 +239,14 @@ ccs_status ccs_scene_create(const ccs_scene_desc* desc, ccs_scene** out) {
     return fail(CCS_ERR_INVALID_ARG, "control_points or patch_types is NULL");
   if (n >= (1u << 31)) return fail(CCS_ERR_INVALID_ARG, "n_patches must be below 2^31");
   if (desc->leaf_depth < 1 || desc->leaf_depth > CCS_MAX_LEAF_DEPTH)
-    return fail(CCS_ERR_INVALID_ARG, "leaf_depth must be in [1, 16]");
+    return fail(CCS_ERR_INVALID_ARG, "leaf_depth must be in [1, " + std::to_string(CCS_MAX_LEAF_DEPTH) + "]");
   if (desc->location != CCS_HOST && desc->location != CCS_DEVICE)
     return fail(CCS_ERR_INVALID_ARG, "location must be CCS_HOST or CCS_DEVICE");
   if ((desc->flags & ~(CCS_FLAG_LOCAL_FRAMES | CCS_FLAG_SINGLE_BOX)) != 0)
     return fail(CCS_ERR_UNSUPPORTED, "unknown flags");
+  if ((desc->flags & CCS_FLAG_SINGLE_BOX) && desc->leaf_depth > ccs::kMaxLeafDepth32)
+    return fail(CCS_ERR_UNSUPPORTED, "the single-box ablation supports leaf depths up to " +
+                                         std::to_string(ccs::kMaxLeafDepth32));
 
   // host-side validation needs no GPU; device input is fetched first
   std::vector<float> cp;
@@ -606,7 +609,8 @@ ccs_status ccs_scene_get_launch(const ccs_scene* s, ccs_launch_params* p) {
   if (!s || !p) return fail(CCS_ERR_INVALID_ARG, "scene or params is NULL");
   *p = s->launch;
   if (p->waves_per_cu == 0)
-    p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false, s->dev.policy.w != nullptr, s->dev.single_box);
+    p->waves_per_cu = (uint32_t)ccs::max_waves_per_cu(false, s->dev.policy.w != nullptr, s->dev.single_box,
+                                                      s->dev.leaf_depth > (int)ccs::kMaxLeafDepth32);
   return CCS_OK;
 }
 
@@ -652,6 +656,8 @@ ccs_status ccs_debug_grids(const ccs_scene* s, uint32_t frame, const uint32_t* p
   if (frame >= s->dev.n_frames) return fail(CCS_ERR_INVALID_ARG, "frame out of range");
   if (n == 0) return CCS_OK;
   if (!patch_ids || !codes || !depths || !out) return fail(CCS_ERR_INVALID_ARG, "a pointer is NULL");
+  if (s->dev.leaf_depth > (int)ccs::kMaxLeafDepth32)
+    return fail(CCS_ERR_UNSUPPORTED, "32-bit path codes: leaf depths up to " + std::to_string(ccs::kMaxLeafDepth32));
   ccs::DeviceScene f = s->dev;
   f.recs = s->dev.recs + frame * s->dev.frame_rec_floats;
   hipError_t e = ccs::launch_debug_grids(f, patch_ids, codes, depths, n, out, (hipStream_t)stream);
@@ -668,6 +674,9 @@ ccs_status ccs_scene_set_policy(ccs_scene* s, const float* params, void* stream)
     return CCS_OK;
   }
   if (s->dev.single_box) return fail(CCS_ERR_UNSUPPORTED, "the single-box ablation has no learned order");
+  if (s->dev.leaf_depth > (int)ccs::kMaxLeafDepth32)
+    return fail(CCS_ERR_UNSUPPORTED, "the learned order supports leaf depths up to " +
+                                         std::to_string(ccs::kMaxLeafDepth32));
   if (s->bvh_depth >= ccs::kMaxBvhDepthLearned)
     return fail(CCS_ERR_UNSUPPORTED, "BVH depth " + std::to_string(s->bvh_depth) +
                                          " exceeds the learned-order kernel's node stack");

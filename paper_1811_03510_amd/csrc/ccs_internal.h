@@ -71,7 +71,10 @@ struct LaunchParams {
 constexpr uint32_t kMaxBvhDepth = 48;
 constexpr uint32_t kMaxBvhDepthLearned = 32;
 
-int max_waves_per_cu(bool counted, bool learned, bool single_box);
+// Leaf depths up to kMaxLeafDepth32 run with 32-bit path codes; deeper ones (up to
+// CCS_MAX_LEAF_DEPTH) with 64-bit codes, closest-first order only.
+constexpr uint32_t kMaxLeafDepth32 = 16;
+int max_waves_per_cu(bool counted, bool learned, bool single_box, bool deep);
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
                             uint32_t waves_per_cu, hipStream_t stream);
 hipError_t launch_refit(const DeviceScene& s, const float* cp_world, const uint32_t* level_offsets,

@@ -426,5 +426,10 @@ __device__ __forceinline__ uint32_t compact_even(uint32_t x) {
   x = (x | (x >> 8)) & 0x0000FFFFu;
   return x;
 }
+// The same for a 64-bit code (leaf depths above 16): the even bits of the high
+// word follow those of the low word.
+__device__ __forceinline__ uint32_t compact_even(uint64_t x) {
+  return compact_even((uint32_t)x) | (compact_even((uint32_t)(x >> 32)) << 16);
+}
 
 }  // namespace ccs

@@ -98,7 +98,7 @@ __device__ __forceinline__ void write_hit(const BatchTable& bt, uint32_t* __rest
 // enters the lower half with the upper one pending; a missed box backtracks, and
 // a hit leaf box is recorded at its own entry distance.  No distance orders the
 // halves, and every pending half costs a grid recompute.
-template <bool kStats, bool kLearned, bool kSingle>
+template <bool kStats, bool kLearned, bool kSingle, typename CodeT>
 __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
                                            LaunchParams lp) {
   constexpr int kStack = kLearned ? (int)kMaxBvhDepthLearned : (int)kMaxBvhDepth;
@@ -129,7 +129,8 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
   uint32_t rec_idx = 0, pmeta = 0;  // current patch record and its meta bits (index | Gregory bit)
   Grid G;
   float dx = 0.0f, dy = 0.0f, dz = 0.0f;
-  uint32_t code = 0, trail = 0, mirror = 0;
+  CodeT code = 0, trail = 0;  // 32 bits for L <= 16, 64 bits beyond
+  uint32_t mirror = 0;
   int depth = 0;
   uint32_t vpref = 0;  // learned order: bit 0 set = take the v-half in bit 1 at the next split
   float pad2 = 0.0f;   // patch-local frames: twice the current patch's box pad (added to d)
@@ -226,7 +227,8 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
             piy = wr.iy;
             piz = wr.iz;
           }
-          code = trail = mirror = 0;
+          code = trail = 0;
+          mirror = 0;
           depth = 0;
           if (pmeta & kGregoryBit) {
             if (kStats) cnt.cand_greg++;
@@ -296,7 +298,9 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
       const uint32_t dg = (uint32_t)depth | ((pmeta & kGregoryBit) ? 0x100u : 0u);
       const uint32_t h_lo = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)rp);
       const uint32_t h_hi = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(rp >> 32));
-      const uint32_t h_code = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)code);
+      CodeT h_code = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)code);
+      if constexpr (sizeof(CodeT) == 8)
+        h_code |= (CodeT)(uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(code >> 32)) << 32;
       const uint32_t h_dg = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)dg);
       float qo[4][4], dc;
       {
@@ -367,7 +371,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
         if (mode == kDecide) {
           const float4 lg = reinterpret_cast<const float4*>(s_feat)[4 * slot];
           const uint32_t top = policy_top(lg.x, lg.y, lg.z, lg.w);
-          const uint32_t bit = 1u << (L2 - depth);  // path bit of the u-split just taken
+          const CodeT bit = (CodeT)1 << (L2 - depth);  // path bit of the u-split just taken
           vpref = 1u | ((top & 1u) << 1);
           if (((top >> 1) != 0) != ((code & bit) != 0)) {
             code ^= bit;  // the other u-half first; the trail bit keeps the closest-first one pending
@@ -415,7 +419,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
           take_half(ex, second, G.x);
           take_half(ey, second, G.y);
           take_half(ez, second, G.z);
-          trail |= 1u << (L2 - 1 - depth);
+          trail |= (CodeT)1 << (L2 - 1 - depth);
           if (second) mirror ^= (1u << axis);
           depth++;
           backtrack = false;
@@ -440,7 +444,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
         const bool h_lo = mir ? hb : ha, h_up = mir ? ha : hb;
         const float t_lo = mir ? tb : ta, t_up = mir ? ta : tb;
         bool go_up = h_up && (!h_lo || t_up < t_lo);
-        const uint32_t bit = 1u << (L2 - 1 - depth);
+        const CodeT bit = (CodeT)1 << (L2 - 1 - depth);
         const uint32_t mirror0 = mirror;
         bool decide = false;
         if (kLearned) {
@@ -471,7 +475,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
             const float tf = pt0 + (go_up ? t_up : t_lo);
             const uint32_t pid = pmeta & kIdMask;
             if (tf < best_t || (tf == best_t && pid < best_id)) {
-              const uint32_t lc = code | (go_up ? bit : 0u);
+              const CodeT lc = code | (go_up ? bit : (CodeT)0);
               best_t = tf;
               best_id = pid;
               s_uv[0][lane] = (float)(2u * compact_even(lc >> 1) + 1u) * (0.5f * leaf_scale);
@@ -491,10 +495,10 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
       }
       if (backtrack) {
         if (trail != 0) {
-          const int b = __builtin_ctz(trail);
-          const uint32_t tb_bit = 1u << b;
+          const int b = sizeof(CodeT) == 8 ? __builtin_ctzll((uint64_t)trail) : __builtin_ctz((uint32_t)trail);
+          const CodeT tb_bit = (CodeT)1 << b;
           trail ^= tb_bit;
-          code = (code ^ tb_bit) & ~(tb_bit - 1u);
+          code = (code ^ tb_bit) & ~(tb_bit - 1);
           depth = L2 - b;
           mode = kGrid;
           if (kStats) cnt.backtrack++;
@@ -516,13 +520,20 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
 template <bool kStats, bool kLearned>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace(DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters,
                                                   LaunchParams lp) {
-  trace_body<kStats, kLearned, false>(s, bt, counters, lp);
+  trace_body<kStats, kLearned, false, uint32_t>(s, bt, counters, lp);
+}
+
+// Leaf depths above 16: the path and trail words in 64 bits (closest-first order only).
+template <bool kStats>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_deep(
+    DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters, LaunchParams lp) {
+  trace_body<kStats, false, false, uint64_t>(s, bt, counters, lp);
 }
 
 template <bool kStats>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_trace_single_box(
     DeviceScene s, BatchTable bt, uint32_t* __restrict__ counters, LaunchParams lp) {
-  trace_body<kStats, false, true>(s, bt, counters, lp);
+  trace_body<kStats, false, true, uint32_t>(s, bt, counters, lp);
 }
 
 // Grid of a subdomain by both of the kernel's routes, for measuring their fp32
@@ -621,13 +632,15 @@ hipError_t launch_debug_grids(const DeviceScene& s, const uint32_t* patch, const
 
 __global__ void k_queue_reset(uint32_t* q) { *q = 0u; }
 
-template <bool kStats, bool kLearned, bool kSingle>
+template <bool kStats, bool kLearned, bool kSingle, bool kDeep>
 static int resident_waves_per_cu() {
   static int per_cu = -1;
   if (per_cu < 0) {
     int v = 0;
     if (kSingle)
       (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace_single_box<kStats>, kBlock, 0);
+    else if (kDeep)
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace_deep<kStats>, kBlock, 0);
     else
       (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_trace<kStats, kLearned>, kBlock, 0);
     per_cu = std::max(1, v);
@@ -635,10 +648,14 @@ static int resident_waves_per_cu() {
   return per_cu;
 }
 
-int max_waves_per_cu(bool counted, bool learned, bool single_box) {
-  if (single_box) return counted ? resident_waves_per_cu<true, false, true>() : resident_waves_per_cu<false, false, true>();
-  if (learned) return counted ? resident_waves_per_cu<true, true, false>() : resident_waves_per_cu<false, true, false>();
-  return counted ? resident_waves_per_cu<true, false, false>() : resident_waves_per_cu<false, false, false>();
+int max_waves_per_cu(bool counted, bool learned, bool single_box, bool deep) {
+  if (single_box)
+    return counted ? resident_waves_per_cu<true, false, true, false>() : resident_waves_per_cu<false, false, true, false>();
+  if (learned)
+    return counted ? resident_waves_per_cu<true, true, false, false>() : resident_waves_per_cu<false, true, false, false>();
+  if (deep)
+    return counted ? resident_waves_per_cu<true, false, false, true>() : resident_waves_per_cu<false, false, false, true>();
+  return counted ? resident_waves_per_cu<true, false, false, false>() : resident_waves_per_cu<false, false, false, false>();
 }
 
 hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t* counters, const LaunchParams& lp,
@@ -646,13 +663,20 @@ hipError_t launch_intersect(const DeviceScene& s, const BatchTable& bt, uint32_t
   const uint32_t n = bt.prefix[bt.n_batches];
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, stream, lp.queue);
-  const bool learned = s.policy.w != nullptr && !s.single_box;
-  int per_cu = max_waves_per_cu(counters != nullptr, learned, s.single_box);
+  // the host refuses the learned order and the single-box ablation above kMaxLeafDepth32
+  const bool deep = s.leaf_depth > (int)kMaxLeafDepth32;
+  const bool learned = s.policy.w != nullptr && !s.single_box && !deep;
+  int per_cu = max_waves_per_cu(counters != nullptr, learned, s.single_box && !deep, deep);
   if (waves_per_cu > 0) per_cu = std::min(per_cu, (int)waves_per_cu);
   const uint32_t waves = (uint32_t)(per_cu * s.n_cus);
   const uint32_t needed = (n + kBlock - 1) / kBlock;
   const dim3 grid(std::min(waves, needed)), block(kBlock);
-  if (s.single_box) {
+  if (deep) {
+    if (counters)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_deep<true>), grid, block, 0, stream, s, bt, counters, lp);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_deep<false>), grid, block, 0, stream, s, bt, nullptr, lp);
+  } else if (s.single_box) {
     if (counters)
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_trace_single_box<true>), grid, block, 0, stream, s, bt, counters, lp);
     else

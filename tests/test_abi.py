@@ -56,7 +56,7 @@ def test_host_validation_errors():
     assert ccs.lib().ccs_scene_create(C.byref(host_desc(cp, ty)), None) == ccs.CCS_ERR_INVALID_ARG
     st, msg, h = create(host_desc(None, ty))
     assert st == ccs.CCS_ERR_INVALID_ARG and h.value is None
-    for L in (0, 17, 100):
+    for L in (0, 21, 23, 100):
         st, msg, _ = create(host_desc(cp, ty, L=L))
         assert st == ccs.CCS_ERR_INVALID_ARG and "leaf_depth" in msg
     bad = ty.copy()

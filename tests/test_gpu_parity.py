@@ -64,6 +64,32 @@ def test_torus512_all_rays(ccs, c1, c1_ref, c1_gpu, cls):
     assert_gate(gate(g, o, rays, c1_oracle, c1.diameter, c1.leaf_depth, label=f"torus512-{cls}"))
 
 
+@pytest.mark.parametrize("L", [17, 18, 20])
+def test_torus512_deep_leaf_depths(ccs, c1, L, frames):
+    """Leaf depths above 16 (64-bit path and trail words): every torus ray against the
+    oracle at the same L, in both frame modes; the variants kept to 32-bit words refuse
+    such a scene."""
+    rays = np.concatenate([c1.primary, c1.diffuse])
+    gsc = ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), L, local_frames=frames)
+    osc = O.Scene(c1.cp, c1.types, L, local_frames=frames)
+    _say(f"torus512 at L = {L}: {len(rays)} rays")
+    g = run(gsc, rays)
+    o = osc.intersect(rays)
+    assert_gate(gate(g, o, rays, osc, c1.diameter, L, label=f"torus512-L{L}"))
+    hit = ids_of(g) != O.NO_HIT
+    assert hit.sum() > 10000
+    # reported (u, v) are centres of leaves of size 2^-L
+    k = g[hit, 2:4].astype(np.float64) * 2.0 ** L - 0.5
+    assert np.array_equal(k, np.round(k))
+    theta = torch.zeros(ccs.POLICY_PARAMS, dtype=torch.float32, device="cuda")
+    with pytest.raises(ccs.CcsError):
+        gsc.set_policy(theta)
+    with pytest.raises(ccs.CcsError):
+        gsc.debug_grids(np.zeros(1, np.uint32), np.zeros(1, np.uint32), np.zeros(1, np.uint32))
+    with pytest.raises(ccs.CcsError):
+        ccs.Scene(torch.from_numpy(c1.cp).cuda(), torch.from_numpy(c1.types).cuda(), L, single_box=True)
+
+
 def test_ragged_launches_are_bitwise_identical(ccs, c1, c1_gpu):
     """Per-ray results do not depend on the launch size or the ray's position in it."""
     rays = c1.diffuse
@@ -124,7 +150,7 @@ def affine_cp(rng):
     return np.concatenate([g, g[[5, 6, 9, 10]]])
 
 
-@pytest.mark.parametrize("L", [1, 4, 12, 16])
+@pytest.mark.parametrize("L", [1, 4, 12, 16, 17, 20])
 def test_single_patches_and_special_rays(ccs, L, frames):
     rng = np.random.default_rng(L)
     for trial in range(4):
