@@ -174,7 +174,7 @@ def test_single_patches_and_special_rays(ccs, L, frames):
         g = run(gsc, rays)
         o = osc.intersect(rays)
         diam = float(np.linalg.norm(np.ptp(cp.reshape(-1, 3).astype(np.float64), axis=0)))
-        assert_gate(gate(g, o, rays, osc, diam, L, min_match=0.99, label=f"single-L{L}-{trial}"))
+        assert_gate(gate(g, o, rays, osc, diam, L, label=f"single-L{L}-{trial}"))
         assert np.all(ids_of(g)[[257, 258, 259]] == O.NO_HIT)
 
 
