@@ -144,6 +144,11 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
     uint64_t mg = __ballot(mode == kGrid);
     if (kLearned) ms |= __ballot(mode == kDecide);  // lanes that will step once decided
 
+    // Wave priority: a wave in the fetch or traversal phase is about to wait on a
+    // chain of dependent loads (queue atomic and ray, or node after node), so it
+    // issues ahead of waves in the arithmetic phases of the same SIMD and its loads
+    // leave earlier; results do not depend on it.
+    __builtin_amdgcn_s_setprio(1);
     // ------------------------------------------------------------ fetch rays
     if (mf != 0 && ((uint32_t)__popcll(mf) >= lp.fetch_min || (mt | ms | mg) == 0)) {
       const int leader = __ffsll((unsigned long long)mf) - 1;
@@ -193,6 +198,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
       mt = __ballot(mode == kTraverse);
     }
 
+    __builtin_amdgcn_s_setprio(2);
     // ------------------------------------------- traverse to the next candidate
     if (mt != 0 && ((uint32_t)__popcll(mt) >= lp.traverse_min || (ms | mg) == 0)) {
       // at most traverse_steps node visits per phase: lanes still walking keep their
@@ -277,6 +283,7 @@ __device__ __forceinline__ void trace_body(DeviceScene s, BatchTable bt, uint32_
       mg = __ballot(mode == kGrid);
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // ---------------------------------------------- recompute grids in a batch
     // Three lanes per waiting lane: the lane of rank r among those waiting (the
     // owner) has the x, y and z components of its grid computed by lanes 3r, 3r+1
