@@ -144,7 +144,7 @@ def tune(scene, batches, reps: int = 5, sweeps: int = 2, log=None, space=None,
         for extra in (dict(DEFAULT),) + tuple(dict(p) for p in PRESETS):
             if extra not in cands:
                 cands.append(extra)
-        best, best_ms = confirm(scene, batches, cands, rounds=7, log=log)
+        best, best_ms = confirm(scene, batches, cands, rounds=15, log=log)
     scene.set_launch(**best)
     return best, best_ms, trials
 
