@@ -15,8 +15,10 @@ library defaults:
                    (searched only when the scene has a learned order)
 
 timing the caller's workload (a list of batches for one ccs_intersect_batched
-call) with HIP events, median of a few repetitions.  The winner is cached in a
-JSON file keyed by GPU architecture, library source hash and a workload key.
+call) with HIP events, median of a few repetitions.  The fastest settings seen
+are then timed again side by side with the library defaults, which they replace
+only when faster by more than 0.5 %.  The winner is cached in a JSON file keyed
+by GPU architecture, library source hash and a workload key.
 """
 from __future__ import annotations
 
@@ -79,9 +81,12 @@ def time_launch(scene, batches, reps: int = 3) -> float:
     return statistics.median(ts)
 
 
-def confirm(scene, batches, cands: list, rounds: int = 5, log=None) -> tuple[dict, float]:
+def confirm(scene, batches, cands: list, rounds: int = 5, log=None, prefer: dict | None = None,
+            margin: float = 0.005) -> tuple[dict, float]:
     """The fastest of ``cands`` by the median of ``rounds`` timings each, taken
-    round-robin so that clock drift affects every candidate alike."""
+    round-robin so that clock drift affects every candidate alike.  ``prefer`` (one
+    of ``cands``) is kept unless another candidate is faster by more than ``margin``
+    (a fraction of its time), so that noise alone does not move the choice."""
     times = [[] for _ in cands]
     for _ in range(rounds):
         for i, p in enumerate(cands):
@@ -89,6 +94,10 @@ def confirm(scene, batches, cands: list, rounds: int = 5, log=None) -> tuple[dic
             times[i].append(time_launch(scene, batches, 1))
     med = [statistics.median(t) for t in times]
     k = min(range(len(cands)), key=lambda i: med[i])
+    if prefer in cands:
+        j = cands.index(prefer)
+        if med[k] > med[j] * (1.0 - margin):
+            k = j
     if log:
         for p, m in zip(cands, med):
             log(f"autotune confirm {p} -> {m:.3f} ms")
@@ -144,7 +153,7 @@ def tune(scene, batches, reps: int = 5, sweeps: int = 2, log=None, space=None,
         for extra in (dict(DEFAULT),) + tuple(dict(p) for p in PRESETS):
             if extra not in cands:
                 cands.append(extra)
-        best, best_ms = confirm(scene, batches, cands, rounds=15, log=log)
+        best, best_ms = confirm(scene, batches, cands, rounds=15, log=log, prefer=dict(DEFAULT))
     scene.set_launch(**best)
     return best, best_ms, trials
 

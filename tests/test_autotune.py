@@ -84,3 +84,21 @@ def test_results_are_cached_by_key(monkeypatch, tmp_path):
     assert autotune.tuned(sc2, [], name="x") == p and sc2.calls == 0 and sc2.p == p
     autotune.tuned(sc2, [], name="y")  # another workload name: tuned again
     assert sc2.calls > 0 and len(json.loads((tmp_path / "cache.json").read_text())) == 2
+
+
+def test_confirmation_keeps_the_default_within_the_margin(monkeypatch):
+    # a finalist 0.2 % faster than the library default does not replace it (noise alone
+    # must not move the choice); one 2 % faster does
+    other = dict(autotune.DEFAULT, fetch_min=24)
+
+    def timed(gain):
+        def t(scene, batches, reps=3):
+            return 1.0 - gain if scene.p == other else 1.0
+        return t
+    monkeypatch.setattr(autotune, "time_launch", timed(0.002))
+    sc = FakeScene()
+    p, ms = autotune.confirm(sc, [], [other, dict(autotune.DEFAULT)], rounds=3, prefer=dict(autotune.DEFAULT))
+    assert p == autotune.DEFAULT and sc.p == autotune.DEFAULT and ms == pytest.approx(1.0)
+    monkeypatch.setattr(autotune, "time_launch", timed(0.02))
+    p, ms = autotune.confirm(sc, [], [other, dict(autotune.DEFAULT)], rounds=3, prefer=dict(autotune.DEFAULT))
+    assert p == other and sc.p == other and ms == pytest.approx(0.98)
